@@ -1,0 +1,336 @@
+/*
+ * Reference oracle for the BLAS pattern compositions of Steuwer, Fensch and
+ * Dubach, "Patterns and Rewrite Rules for Systematic Code Generation"
+ * (arXiv 1502.02389).  TEST INFRASTRUCTURE ONLY: the tests, the smoke check
+ * and the CPU-baseline leg of the benchmark call this code; the GPU library
+ * never does, and the two share no source.
+ *
+ * Everything is evaluated in IEEE binary64 with no fusion, blocking or
+ * reordering beyond what the pattern definitions state:
+ *
+ *   map(f)         T[n] -> U[n], f applied to every element     (Table 1)
+ *   zip(a, b)      a:T[n], b:U[n] -> <T,U>[n]                    (Table 1)
+ *   reduce(f, z)   T[] -> T[1]; evaluated as the sequential left fold
+ *                  acc = z; acc = f(acc, a_i) for i = 0..n-1, which is the
+ *                  one reduction the paper lowers to (reduce-seq, Table 2
+ *                  and the reduction lowering rule of Fig. 4b)
+ *
+ * and the four linear-algebra programs are the literal compositions of the
+ * BLAS figure (Fig. 5, Section 5.1):
+ *
+ *   abs(x)            = if x < 0 then -x else x
+ *   scal(a, x)        = map(mult(a), x)
+ *   asum(x)           = reduce(add, 0) . map(abs, x)
+ *   dot(x, y)         = reduce(add, 0) . map(mult) . zip(x, y)
+ *   gemv(A, x, y, a, b):
+ *       z  = map(scal(a) . dot(x), A)            (one dot per row of A)
+ *       y' = map(add) . zip(z, scal(b, y))
+ *
+ * Readings where the paper is silent:
+ *   - storage types f32 / bf16 / f16 are widened EXACTLY to binary64 as the
+ *     first map; every result is binary64 (the caller rounds if it wants);
+ *   - gemv follows the BLAS convention that beta == 0 means y is not read
+ *     (NaN/Inf in y do not propagate); for beta != 0 it is the literal
+ *     composition above;
+ *   - A is row-major with leading dimension lda >= n (map over rows).
+ *
+ * Pins (see tests/test_oracle_blas.py): closed forms, exact integer sums,
+ * math.fsum (correctly rounded) within the sequential-fold error bound,
+ * Hadamard orthogonality, brute force with Python Fractions, and the
+ * decoders against numpy / torch for all 65536 16-bit patterns.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+enum { OR_F32 = 0, OR_BF16 = 1, OR_F16 = 2, OR_F64 = 3 };
+enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2 };
+
+/* ------------------------------------------------------------------ */
+/* exact storage decoders (IEEE 754 binary32 / binary16, bfloat16)     */
+/* ------------------------------------------------------------------ */
+
+static double decode_f32(uint32_t bits)
+{
+    float f;
+    memcpy(&f, &bits, sizeof f);
+    return (double)f; /* binary32 -> binary64 is exact */
+}
+
+/* bfloat16 is the upper half of a binary32 encoding. */
+static double decode_bf16(uint16_t h)
+{
+    return decode_f32((uint32_t)h << 16);
+}
+
+/* binary16: 1 sign bit, 5 exponent bits (bias 15), 10 fraction bits. */
+static double decode_f16(uint16_t h)
+{
+    int sign = (h >> 15) & 1;
+    int e = (h >> 10) & 0x1f;
+    int m = h & 0x3ff;
+    double v;
+    if (e == 0)
+        v = ldexp((double)m, -24);              /* zero / subnormal */
+    else if (e == 31)
+        v = m ? NAN : INFINITY;
+    else
+        v = ldexp((double)(1024 + m), e - 25);  /* (1.m) * 2^(e-15) */
+    return sign ? -v : v;
+}
+
+static double load_elem(int dtype, const void *base, int64_t i)
+{
+    switch (dtype) {
+    case OR_F32: {
+        uint32_t b;
+        memcpy(&b, (const char *)base + 4 * i, 4);
+        return decode_f32(b);
+    }
+    case OR_BF16: {
+        uint16_t b;
+        memcpy(&b, (const char *)base + 2 * i, 2);
+        return decode_bf16(b);
+    }
+    case OR_F16: {
+        uint16_t b;
+        memcpy(&b, (const char *)base + 2 * i, 2);
+        return decode_f16(b);
+    }
+    default:
+        return ((const double *)base)[i];
+    }
+}
+
+static int valid_dtype(int t) { return t >= OR_F32 && t <= OR_F64; }
+
+/* ------------------------------------------------------------------ */
+/* high-level patterns (Table 1) over binary64 arrays                  */
+/* ------------------------------------------------------------------ */
+
+typedef double (*unary_fn)(double v, const void *env);
+typedef double (*binary_fn)(double a, double b, const void *env);
+typedef struct { double a, b; } pair_t;
+
+/* map(f): out[i] = f(in[i]) */
+static void map1(int64_t n, const double *in, double *out, unary_fn f, const void *env)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = f(in[i], env);
+}
+
+/* zip(a, b): out[i] = <a[i], b[i]> */
+static void zip(int64_t n, const double *a, const double *b, pair_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        out[i].a = a[i];
+        out[i].b = b[i];
+    }
+}
+
+/* map(f) over an array of pairs, f taking the pair's two components */
+static void map_pairs(int64_t n, const pair_t *in, double *out, binary_fn f, const void *env)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = f(in[i].a, in[i].b, env);
+}
+
+/* reduce(f, z): sequential left fold from index 0 */
+static double reduce(int64_t n, const double *in, binary_fn f, double z, const void *env)
+{
+    double acc = z;
+    for (int64_t i = 0; i < n; ++i)
+        acc = f(acc, in[i], env);
+    return acc;
+}
+
+/* widening map: the exact conversion of the stored type to binary64 */
+static void widen(int64_t n, int dtype, const void *src, int64_t stride, double *dst)
+{
+    for (int64_t i = 0; i < n; ++i)
+        dst[i] = load_elem(dtype, src, i * stride);
+}
+
+/* ------------------------------------------------------------------ */
+/* user functions of the BLAS figure                                    */
+/* ------------------------------------------------------------------ */
+
+static double fn_add(double x, double y, const void *env) { (void)env; return x + y; }
+static double fn_mult(double x, double y, const void *env) { (void)env; return x * y; }
+static double fn_abs(double x, const void *env) { (void)env; return (x < 0) ? -x : x; }
+/* mult(a) with a bound as the first argument (partial application) */
+static double fn_mult_bound(double x, const void *env) { return *(const double *)env * x; }
+/* |a*b|: used only for the error-bound denominators below */
+static double fn_absmult(double x, double y, const void *env)
+{
+    (void)env;
+    double p = x * y;
+    return (p < 0) ? -p : p;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported entry points                                                */
+/* ------------------------------------------------------------------ */
+
+int oracle_widen(int64_t n, int dtype, const void *x, double *out)
+{
+    if (n < 0 || !valid_dtype(dtype) || (n > 0 && (!x || !out)))
+        return OR_EINVAL;
+    widen(n, dtype, x, 1, out);
+    return OR_OK;
+}
+
+/* scal(a, x) = map(mult(a), x) */
+int oracle_scal(int64_t n, double alpha, int xt, const void *x, double *out)
+{
+    if (n < 0 || !valid_dtype(xt) || (n > 0 && (!x || !out)))
+        return OR_EINVAL;
+    double *w = malloc((size_t)(n ? n : 1) * sizeof *w);
+    if (!w)
+        return OR_ENOMEM;
+    widen(n, xt, x, 1, w);
+    map1(n, w, out, fn_mult_bound, &alpha);
+    free(w);
+    return OR_OK;
+}
+
+/* asum(x) = reduce(add, 0) . map(abs, x) */
+int oracle_asum(int64_t n, int xt, const void *x, double *result)
+{
+    if (n < 0 || !valid_dtype(xt) || !result || (n > 0 && !x))
+        return OR_EINVAL;
+    double *w = malloc((size_t)(n ? n : 1) * sizeof *w);
+    double *t = malloc((size_t)(n ? n : 1) * sizeof *t);
+    if (!w || !t) {
+        free(w);
+        free(t);
+        return OR_ENOMEM;
+    }
+    widen(n, xt, x, 1, w);
+    map1(n, w, t, fn_abs, NULL);
+    *result = reduce(n, t, fn_add, 0.0, NULL);
+    free(w);
+    free(t);
+    return OR_OK;
+}
+
+/* reduce(add, 0) . map(g) . zip(x, y) on already-widened operands */
+static double dot_widened(int64_t n, const double *wx, const double *wy, binary_fn g,
+                          pair_t *zbuf, double *pbuf)
+{
+    zip(n, wx, wy, zbuf);
+    map_pairs(n, zbuf, pbuf, g, NULL);
+    return reduce(n, pbuf, fn_add, 0.0, NULL);
+}
+
+static int dot_common(int64_t n, int xt, const void *x, int yt, const void *y,
+                      binary_fn g, double *result)
+{
+    if (n < 0 || !valid_dtype(xt) || !valid_dtype(yt) || !result || (n > 0 && (!x || !y)))
+        return OR_EINVAL;
+    size_t m = (size_t)(n ? n : 1);
+    double *wx = malloc(m * sizeof *wx);
+    double *wy = malloc(m * sizeof *wy);
+    pair_t *z = malloc(m * sizeof *z);
+    double *p = malloc(m * sizeof *p);
+    int rc = OR_OK;
+    if (!wx || !wy || !z || !p) {
+        rc = OR_ENOMEM;
+    } else {
+        widen(n, xt, x, 1, wx);
+        widen(n, yt, y, 1, wy);
+        *result = dot_widened(n, wx, wy, g, z, p);
+    }
+    free(wx);
+    free(wy);
+    free(z);
+    free(p);
+    return rc;
+}
+
+/* dot(x, y) = reduce(add, 0) . map(mult) . zip(x, y) */
+int oracle_dot(int64_t n, int xt, const void *x, int yt, const void *y, double *result)
+{
+    return dot_common(n, xt, x, yt, y, fn_mult, result);
+}
+
+/* sum_i |x_i * y_i|: the condition denominator used to state dot's error */
+int oracle_dot_absmass(int64_t n, int xt, const void *x, int yt, const void *y, double *result)
+{
+    return dot_common(n, xt, x, yt, y, fn_absmult, result);
+}
+
+static int gemv_common(int64_t m, int64_t n, double alpha, int at, const void *A, int64_t lda,
+                       int xt, const void *x, double beta, int yt, const void *y,
+                       binary_fn g, int absolute, double *out)
+{
+    if (m < 0 || n < 0 || lda < (n > 1 ? n : 1) || !valid_dtype(at) || !valid_dtype(xt) ||
+        !valid_dtype(yt) || (m > 0 && !out) || (m > 0 && n > 0 && (!A || !x)) ||
+        (m > 0 && beta != 0.0 && !y))
+        return OR_EINVAL;
+    size_t nn = (size_t)(n ? n : 1);
+    double *wx = malloc(nn * sizeof *wx);
+    double *row = malloc(nn * sizeof *row);
+    pair_t *zb = malloc(nn * sizeof *zb);
+    double *pb = malloc(nn * sizeof *pb);
+    size_t mm = (size_t)(m ? m : 1);
+    double *z = malloc(mm * sizeof *z);
+    double *wy = malloc(mm * sizeof *wy);
+    double *by = malloc(mm * sizeof *by);
+    pair_t *zz = malloc(mm * sizeof *zz);
+    int rc = OR_OK;
+    if (!wx || !row || !zb || !pb || !z || !wy || !by || !zz) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    widen(n, xt, x, 1, wx);
+    /* z = map(scal(a) . dot(x), A): one dot per row, then multiply by a */
+    size_t esz = (at == OR_F32) ? 4 : (at == OR_F64) ? 8 : 2;
+    for (int64_t i = 0; i < m; ++i) {
+        if (n > 0)
+            widen(n, at, (const char *)A + (size_t)i * (size_t)lda * esz, 1, row);
+        double d = dot_widened(n, wx, row, g, zb, pb);
+        double a = absolute ? fabs(alpha) : alpha;
+        double one[1] = {d}, scaled[1];
+        map1(1, one, scaled, fn_mult_bound, &a); /* scal(a) of the length-1 dot */
+        z[i] = scaled[0];
+    }
+    /* y' = map(add) . zip(z, scal(b, y)); beta == 0 leaves y unread */
+    if (beta == 0.0) {
+        for (int64_t i = 0; i < m; ++i)
+            by[i] = 0.0;
+    } else {
+        double b = absolute ? fabs(beta) : beta;
+        widen(m, yt, y, 1, wy);
+        if (absolute)
+            map1(m, wy, wy, fn_abs, NULL);
+        map1(m, wy, by, fn_mult_bound, &b);
+    }
+    zip(m, z, by, zz);
+    map_pairs(m, zz, out, fn_add, NULL);
+done:
+    free(wx);
+    free(row);
+    free(zb);
+    free(pb);
+    free(z);
+    free(wy);
+    free(by);
+    free(zz);
+    return rc;
+}
+
+/* gemv: y' = alpha * A x + beta * y, row-major A with leading dimension lda */
+int oracle_gemv(int64_t m, int64_t n, double alpha, int at, const void *A, int64_t lda,
+                int xt, const void *x, double beta, int yt, const void *y, double *out)
+{
+    return gemv_common(m, n, alpha, at, A, lda, xt, x, beta, yt, y, fn_mult, 0, out);
+}
+
+/* |alpha| * sum_j |A_ij x_j| + |beta y_i|: per-row error denominator for gemv */
+int oracle_gemv_absmass(int64_t m, int64_t n, double alpha, int at, const void *A, int64_t lda,
+                        int xt, const void *x, double beta, int yt, const void *y, double *out)
+{
+    return gemv_common(m, n, alpha, at, A, lda, xt, x, beta, yt, y, fn_absmult, 1, out);
+}

@@ -1,0 +1,102 @@
+"""Planted mistakes in the C oracle must each fail at least one pin.
+
+Each mutant is a one-line textual change to a temporary copy of
+oracle/lift_oracle.c (a dropped term, a wrong sign, a wrong index or stride,
+a transposed operand, a wrong decoder constant), compiled with gcc on the CPU
+and swapped in for the real library while a fast subset of the pins in
+test_oracle_blas.py runs.  The real oracle is untouched.
+"""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_blas as pins
+
+SRC = open(os.path.join(os.path.dirname(oracle.__file__), "lift_oracle.c")).read()
+
+MUTANTS = {
+    "reduce_drops_last_term": ("for (int64_t i = 0; i < n; ++i)\n        acc = f(acc, in[i], env);",
+                               "for (int64_t i = 0; i < n - 1; ++i)\n        acc = f(acc, in[i], env);"),
+    "reduce_wrong_start": ("double acc = z;", "double acc = z + 1.0;"),
+    "abs_wrong_sign": ("return (x < 0) ? -x : x; }", "return (x < 0) ? x : x; }"),
+    "dot_adds_instead_of_mult": ("return dot_common(n, xt, x, yt, y, fn_mult, result);",
+                                 "return dot_common(n, xt, x, yt, y, fn_add, result);"),
+    "scal_adds": ("return *(const double *)env * x; }", "return *(const double *)env + x; }"),
+    "gemv_row_stride_n": ("(size_t)i * (size_t)lda * esz, 1, row)", "(size_t)i * (size_t)n * esz, 1, row)"),
+    "gemv_transposed": ("widen(n, at, (const char *)A + (size_t)i * (size_t)lda * esz, 1, row);",
+                        "widen(n, at, (const char *)A + (size_t)i * esz, lda, row);"),
+    "gemv_beta_uses_alpha": ("map1(m, wy, by, fn_mult_bound, &b);", "map1(m, wy, by, fn_mult_bound, &alpha);"),
+    "gemv_drops_alpha": ("map1(1, one, scaled, fn_mult_bound, &a);", "scaled[0] = one[0];"),
+    "f16_wrong_bias": ("e - 25);", "e - 24);"),
+    "f16_subnormal_scale": ("ldexp((double)m, -24)", "ldexp((double)m, -25)"),
+    "bf16_wrong_shift": ("(uint32_t)h << 16", "(uint32_t)h << 15"),
+    "zip_swaps_pairs": ("out[i].a = a[i];\n        out[i].b = b[i];", "out[i].a = a[i];\n        out[i].b = a[i];"),
+}
+
+FAST_PINS = [
+    pins.test_decode_f16_all_patterns,
+    pins.test_decode_bf16_all_patterns,
+    pins.test_scal_rounds_like_one_float32_multiply,
+    pins.test_scal_identity_and_mul3,
+    pins.test_asum_closed_forms,
+    pins.test_asum_brute_force_rational_small,
+    pins.test_dot_orthogonal_closed_forms,
+    pins.test_dot_hadamard_rows,
+    pins.test_dot_brute_force_rational_small_mixed_storage,
+    pins.test_gemv_identity_matrix,
+    pins.test_gemv_alpha_zero_and_beta_zero,
+    pins.test_gemv_brute_force_rational_nonsquare_with_lda,
+    pins.test_gemv_absmass_definition,
+]
+
+
+@pytest.fixture(scope="module")
+def builddir(tmp_path_factory):
+    return tmp_path_factory.mktemp("mutants")
+
+
+def _build(src: str, path: str):
+    c = path + ".c"
+    with open(c, "w") as f:
+        f.write(src)
+    subprocess.run(["gcc", "-O1", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", path, c, "-lm"],
+                   check=True)
+
+
+def test_mutations_apply_cleanly():
+    for name, (old, new) in MUTANTS.items():
+        assert SRC.count(old) == 1, name
+
+
+def test_unmutated_copy_passes_fast_pins(builddir):
+    path = str(builddir / "base.so")
+    _build(SRC, path)
+    saved = oracle._lib
+    try:
+        oracle._lib = oracle._configure(ctypes.CDLL(path))
+        for pin in FAST_PINS:
+            pin()
+    finally:
+        oracle._lib = saved
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, builddir):
+    old, new = MUTANTS[name]
+    path = str(builddir / f"{name}.so")
+    _build(SRC.replace(old, new), path)
+    saved = oracle._lib
+    caught = []
+    try:
+        oracle._lib = oracle._configure(ctypes.CDLL(path))
+        for pin in FAST_PINS:
+            try:
+                pin()
+            except (AssertionError, RuntimeError, ValueError):
+                caught.append(pin.__name__)
+    finally:
+        oracle._lib = saved
+    assert caught, f"mutant {name} survived every pin"

@@ -1,0 +1,141 @@
+"""Seeded synthetic inputs for the paper's linear-algebra workloads.
+
+Shared by the tests, the smoke check and the benchmark; it draws random
+numbers and converts storage types, and holds none of the arithmetic of the
+operations themselves (neither the GPU library nor the oracle is imported).
+
+Every array is generated on the CPU with ``torch.Generator('cpu')`` so the
+oracle and the GPU see identical bits; callers copy to the device.
+
+Recipes (Section 7.2 of the paper fixes the sizes: 16M and 128M-element
+vectors, a 4096x4096 matrix with a 4096-vector, and an 8192x16384 matrix):
+
+* uniform  : ``torch.rand(n) * 2 - 1`` in float32 -- exact multiples of 2^-24
+             in [-1, 1)
+* normal   : ``torch.randn``; draw order A, then x, then y
+* integer  : ``torch.randint(lo, hi + 1).float()`` -- integer-valued floats
+* bf16/f16 : float32 values as above, then ``.to(dtype)`` (round to nearest even)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+STORAGE = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+
+
+def gen(seed: int) -> torch.Generator:
+    g = torch.Generator("cpu")
+    g.manual_seed(seed)
+    return g
+
+
+def uniform(n: int, g: torch.Generator, storage: str = "f32") -> torch.Tensor:
+    return (torch.rand(n, generator=g, dtype=torch.float32) * 2 - 1).to(STORAGE[storage])
+
+
+def normal(shape, g: torch.Generator, storage: str = "f32") -> torch.Tensor:
+    return torch.randn(shape, generator=g, dtype=torch.float32).to(STORAGE[storage])
+
+
+def integers(shape, lo: int, hi: int, g: torch.Generator, storage: str = "f32") -> torch.Tensor:
+    """Integer-valued floats uniform in [lo, hi] (inclusive)."""
+    return torch.randint(lo, hi + 1, shape if isinstance(shape, tuple) else (shape,),
+                         generator=g).to(torch.float32).to(STORAGE[storage])
+
+
+# --------------------------------------------------------------------------
+# the five workload configurations
+# --------------------------------------------------------------------------
+
+CONFIG1_N = 1 << 20            # asum, single vector
+CONFIG2_N = 1 << 24            # scal/asum/dot, 64 MiB per fp32 vector
+CONFIG2_ALPHA = 2.5
+CONFIG3_SIZES = (4096, 8192)   # square gemv
+CONFIG3_ALPHA, CONFIG3_BETA = 1.0, 0.5
+CONFIG4_N = 1 << 26            # 16-bit storage asum/dot
+CONFIG4_GEMV = 16384           # bf16 A, square
+CONFIG5_NRED, CONFIG5_NGEMV = 4096, 256
+
+
+def config1(integer: bool = False):
+    """asum, n = 2^20, seed 0: uniform, or integers in [-8, 8]."""
+    g = gen(0)
+    if integer:
+        return integers(CONFIG1_N, -8, 8, g)
+    return uniform(CONFIG1_N, g)
+
+
+def config2(n: int = CONFIG2_N):
+    """scal/asum/dot vectors x then y, uniform, seed 1; alpha = 2.5."""
+    g = gen(1)
+    x = uniform(n, g)
+    y = uniform(n, g)
+    return x, y, CONFIG2_ALPHA
+
+
+def config3(size: int):
+    """gemv operands A (size x size), x, y ~ normal(0, 1), seed 2."""
+    g = gen(2)
+    A = normal((size, size), g)
+    x = normal(size, g)
+    y = normal(size, g)
+    return A, x, y, CONFIG3_ALPHA, CONFIG3_BETA
+
+
+def config4_vectors(storage: str, n: int = CONFIG4_N):
+    """16-bit-stored x, y for asum/dot, uniform, seed 3."""
+    g = gen(3)
+    x = uniform(n, g, storage)
+    y = uniform(n, g, storage)
+    return x, y
+
+
+def config4_gemv(size: int = CONFIG4_GEMV):
+    """bf16-stored A with fp32 x, y ~ normal, seed 3; alpha 1, beta 0.5."""
+    g = gen(3)
+    A = normal((size, size), g, "bf16")
+    x = normal(size, g)
+    y = normal(size, g)
+    return A, x, y, CONFIG3_ALPHA, CONFIG3_BETA
+
+
+@dataclass
+class BatchSpec:
+    """Shapes of the batched workload: reductions then gemv problems."""
+
+    red_kind: list = field(default_factory=list)   # "dot" or "asum"
+    red_len: list = field(default_factory=list)
+    gemv_mn: list = field(default_factory=list)    # (m, n)
+
+
+def config5_shapes(n_red: int = CONFIG5_NRED, n_gemv: int = CONFIG5_NGEMV,
+                   lo_exp: float = 8.0, hi_exp: float = 20.0,
+                   mn_lo: int = 64, mn_hi: int = 4096, seed: int = 4) -> BatchSpec:
+    """Reduction lengths floor(2^U(lo, hi)) (log-uniform), kinds alternating
+    dot (even index) / asum (odd index); gemv M, N uniform in [mn_lo, mn_hi]."""
+    g = gen(seed)
+    u = torch.rand(n_red, generator=g, dtype=torch.float64) * (hi_exp - lo_exp) + lo_exp
+    lens = [int(math.floor(2.0 ** float(e))) for e in u]
+    kinds = ["dot" if i % 2 == 0 else "asum" for i in range(n_red)]
+    mn = torch.randint(mn_lo, mn_hi + 1, (n_gemv, 2), generator=g)
+    return BatchSpec(kinds, lens, [(int(a), int(b)) for a, b in mn])
+
+
+def config5_values(spec: BatchSpec, storage: str = "f32", seed: int = 5):
+    """Values for a batch: reductions uniform, gemv normal (A, x, y per problem)."""
+    g = gen(seed)
+    reds = []
+    for kind, n in zip(spec.red_kind, spec.red_len):
+        x = uniform(n, g, storage)
+        y = uniform(n, g, storage) if kind == "dot" else None
+        reds.append((kind, x, y))
+    gemvs = []
+    for m, n in spec.gemv_mn:
+        A = normal((m, n), g, storage)
+        x = normal(n, g)
+        y = normal(m, g)
+        gemvs.append((A, x, y))
+    return reds, gemvs
