@@ -1,0 +1,329 @@
+#!/usr/bin/env python3
+"""Throughput of the map/reduce BLAS hot path on one MI355X.
+
+A step is one pass of scal, asum and dot (binary32, per-call kernels) over
+vectors of n = 2^24 elements (64 MiB each), alpha = 2.5, x and y uniform in
+[-1, 1) from seed 1 -- the paper's "small" 16M-element vector size.  `value`
+is the step's algorithmic HBM bytes (scal reads and writes n floats, asum
+reads n, dot reads 2n: 20n bytes) divided by the measured time per step, in
+GB/s (1e9 B/s).  Inputs are resident in HBM before timing starts; steps
+rotate over enough copies of the buffers (> 1 GiB in total) that no step
+finds its operands in the 256 MB Infinity Cache.
+
+Also reported on the same JSON line:
+  roofline     : the dominant kernel's algorithmic bytes per launch over its
+                 average duration, from HIP events recorded around it on its
+                 stream inside the timed region; peak 8 TB/s; HBM traffic per
+                 launch from rocprofv3 counters when they were taken on the
+                 current kernel source (else null)
+  cpu_baseline : the binary64 oracle (single thread) on a bounded sample of the
+                 same workload, same data
+  kernels      : per-kernel average durations from back-to-back launches
+  forms        : gemv fp32 (4096^2, 8192^2), 16-bit storage (n = 2^26 asum/dot,
+                 bf16 gemv 16384^2) in each accumulation variant, as GB/s and
+                 binary32-equivalent GB/s
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-forms]
+       [--no-cpu-baseline] [--cpu-seconds S]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_GBS = 8000.0
+METRIC = "HBM GB/s and % of 8 TB/s peak: asum/dot/gemv FP32 vs BF16 and batched forms"
+COLD_BYTES = 1 << 30          # rotate buffer sets until at least this much is touched
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of the sources a kernel is built from (device helpers + its unit)."""
+    csrc = os.path.join(ROOT, "paper_1502_02389_amd", "csrc")
+    files = {"scal": ["lift_device.hpp", "lift_internal.hpp", "lift_scal.hip"],
+             "asum": ["lift_device.hpp", "lift_internal.hpp", "lift_reduce.hpp", "lift_reduce_f32.hip"],
+             "dot": ["lift_device.hpp", "lift_internal.hpp", "lift_reduce.hpp", "lift_reduce_f32.hip"],
+             "gemv": ["lift_device.hpp", "lift_internal.hpp", "lift_gemv.hpp", "lift_gemv_f32.hip"]}[kernel]
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current source of that kernel."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this library has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1502_02389_amd as L
+    import workloads as W
+
+    lib = L.library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    props = torch.cuda.get_device_properties(dev)
+    log("device", props.name, "CUs", props.multi_processor_count, "lib", L.lift_version())
+
+    # ------------------------------------------------------------ main step
+    n = W.CONFIG2_N
+    x_cpu, y_cpu, alpha = W.config2(n)
+    x0, y0 = x_cpu.to(dev), y_cpu.to(dev)
+    set_bytes = 5 * 4 * n
+    nsets = max(2, -(-COLD_BYTES // set_bytes))
+    sets = []
+    for _ in range(nsets):
+        sets.append(dict(xs=x0.clone(), out=torch.empty_like(x0), xa=x0.clone(), xd=x0.clone(), yd=y0.clone(),
+                         ra=torch.zeros((), device=dev), rd=torch.zeros((), device=dev)))
+    del x0, y0
+    ws = L.workspace(dev)
+    wsp, wsb = ws.data_ptr(), ws.numel()
+    ptr = [{k: v.data_ptr() for k, v in s.items()} for s in sets]
+    bytes_kernel = {"scal": 8 * n, "asum": 4 * n, "dot": 8 * n}
+    step_bytes = sum(bytes_kernel.values())
+
+    def launch(kernel, p):
+        if kernel == "scal":
+            st = lib.lift_scal(n, alpha, p["xs"], p["out"], sh)
+        elif kernel == "asum":
+            st = lib.lift_asum(n, p["xa"], p["ra"], wsp, wsb, sh)
+        else:
+            st = lib.lift_dot(n, p["xd"], p["yd"], p["rd"], wsp, wsb, sh)
+        if st != 0:
+            raise L.LiftError(st, f"lift_{kernel}")
+
+    order = ("scal", "asum", "dot")
+
+    def step(i, ev_kernel=None, evs=None):
+        p = ptr[i % nsets]
+        for k in order:
+            if k == ev_kernel:
+                e0, e1 = evs
+                e0.record(stream)
+                launch(k, p)
+                e1.record(stream)
+            else:
+                launch(k, p)
+
+    log("warmup", args.warmup, "sets", nsets)
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    # per-kernel durations from back-to-back launches (outside the timed region)
+    kernels = {}
+    reps = 200
+    for k in order:
+        for i in range(5):
+            launch(k, ptr[i % nsets])
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for i in range(reps):
+            launch(k, ptr[i % nsets])
+        t1.record(stream)
+        torch.cuda.synchronize()
+        us = t0.elapsed_time(t1) * 1e3 / reps
+        gbs = bytes_kernel[k] / (us * 1e-6) / 1e9
+        kernels[k] = {"avg_us": round(us, 3), "bytes": bytes_kernel[k], "GB_s": round(gbs, 1),
+                      "frac_of_peak": round(gbs / PEAK_GBS, 4)}
+        log("kernel", k, kernels[k])
+    dominant = max(order, key=lambda k: kernels[k]["avg_us"])
+
+    # timed region: K steps, events around the dominant kernel in each step
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(i, dominant, evs[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    durs = [a.elapsed_time(b) * 1e3 for a, b in evs]
+    dom_us = sum(durs) / len(durs)
+    achieved = bytes_kernel[dominant] / (dom_us * 1e-6) / 1e9
+    log("timed", args.steps, "steps", f"{ms_per_step:.4f} ms/step", f"{value:.1f} GB/s",
+        "dominant", dominant, f"{dom_us:.2f} us")
+
+    roofline = {"bound": "hbm", "kernel": f"lift {dominant} (fp32, n=2^24)", "achieved": round(achieved, 1),
+                "peak": PEAK_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4),
+                "traffic": measured_traffic(dominant), "algorithmic_bytes": bytes_kernel[dominant],
+                "avg_us": round(dom_us, 3), "median_us": round(statistics.median(durs), 3)}
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "scal+asum+dot fp32 per-call kernels, n=2^24 (64 MiB per vector), alpha=2.5, "
+                               "x,y ~ U[-1,1) seed 1, cold Infinity Cache (rotating buffer sets)",
+                   "n": n, "bytes_per_step": step_bytes, "buffer_sets": nsets,
+                   "frac_of_peak": round(value / PEAK_GBS, 4)},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+
+    # ------------------------------------------------------------ CPU oracle
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(x_cpu, y_cpu, alpha, args.cpu_seconds, sets[0], step_bytes)
+
+    # ------------------------------------------------------------ other forms
+    if not args.no_forms:
+        del sets, ptr
+        torch.cuda.empty_cache()
+        result["forms"] = forms(L, W, dev, stream)
+
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(x_cpu, y_cpu, alpha, seconds, gpu_set, step_bytes):
+    """The binary64 oracle, single thread, timed on whole steps of the same
+    workload until `seconds` have elapsed (at least one step)."""
+    import oracle
+
+    xs, ys = x_cpu.numpy(), y_cpu.numpy()
+    oracle.asum(xs[:1024])  # load
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.scal(alpha, xs)
+        ra = oracle.asum(xs)
+        rd = oracle.dot(xs, ys)
+        reps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    gbs = step_bytes * reps / el / 1e9
+    ga, gd = float(gpu_set["ra"].item()), float(gpu_set["rd"].item())
+    mass = oracle.dot_absmass(xs, ys)
+    log("cpu oracle", reps, "steps in", f"{el:.1f}s", f"{gbs:.3f} GB/s")
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full steps (scal+asum+dot, n=2^24) of the binary64 C oracle, one thread, "
+                      f"{el:.1f} s",
+            "gpu_vs_oracle": {"asum_rel_err": abs(ga - ra) / ra, "dot_err_over_absmass": abs(gd - rd) / mass}}
+
+
+def _time_calls(fn, nsets, stream, reps=50, warm=5):
+    """Average device time per call of fn(i) over reps back-to-back calls."""
+    import torch
+
+    for i in range(warm):
+        fn(i % nsets)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(reps):
+        fn(i % nsets)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def forms(L, W, dev, stream):
+    import torch
+
+    lib = L.library()
+    sh = stream.cuda_stream
+    ws = L.workspace(dev)
+    wsp, wsb = ws.data_ptr(), ws.numel()
+    out = {}
+
+    def rec(name, us, nbytes, fp32_bytes):
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out[name] = {"avg_us": round(us, 3), "GB_s": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_GBS, 4),
+                     "fp32_equiv_GB_s": round(fp32_bytes / (us * 1e-6) / 1e9, 1)}
+        log("form", name, out[name])
+
+    # gemv fp32, square 4096 and 8192
+    for size in W.CONFIG3_SIZES:
+        A, x, y, alpha, beta = W.config3(size)
+        nb = 4 * size * size + 4 * size + 8 * size
+        ns = max(2, -(-COLD_BYTES // nb))
+        As = [A.to(dev) for _ in range(ns)]
+        xd, yd = x.to(dev), y.to(dev)
+
+        def call(i, As=As, xd=xd, yd=yd, size=size, alpha=alpha, beta=beta):
+            st = lib.lift_gemv(size, size, alpha, As[i].data_ptr(), size, xd.data_ptr(), beta, yd.data_ptr(), sh)
+            assert st == 0
+        rec(f"gemv_f32_{size}", _time_calls(call, ns, stream), nb, nb)
+        del As
+        torch.cuda.empty_cache()
+
+    # 16-bit storage asum / dot, n = 2^26
+    n = W.CONFIG4_N
+    for storage, code in (("bf16", L.LIFT_BF16), ("f16", L.LIFT_F16)):
+        x, y = W.config4_vectors(storage)
+        ns = max(2, -(-COLD_BYTES // (4 * n)))
+        xs = [x.to(dev) for _ in range(ns)]
+        ys = [y.to(dev) for _ in range(ns)]
+        res = torch.zeros((), dtype=torch.float64, device=dev)
+        for acc_name, acc in (("f32", 0), ("comp", 1), ("f64combine", 2)):
+            def ca(i, acc=acc):
+                assert lib.lift_asum_ex(n, code, xs[i].data_ptr(), acc, L.LIFT_F64, res.data_ptr(), wsp, wsb,
+                                        None, sh) == 0
+
+            def cd(i, acc=acc):
+                assert lib.lift_dot_ex(n, code, xs[i].data_ptr(), ys[i].data_ptr(), acc, L.LIFT_F64,
+                                       res.data_ptr(), wsp, wsb, None, sh) == 0
+            rec(f"asum_{storage}_{acc_name}_2^26", _time_calls(ca, ns, stream), 2 * n, 4 * n)
+            rec(f"dot_{storage}_{acc_name}_2^26", _time_calls(cd, ns, stream), 4 * n, 8 * n)
+        del xs, ys
+        torch.cuda.empty_cache()
+
+    # bf16 gemv 16384^2 (A 512 MiB: larger than the Infinity Cache by itself)
+    A, x, y, alpha, beta = W.config4_gemv()
+    size = A.shape[0]
+    Ad, xd, yd = A.to(dev), x.to(dev), y.to(dev)
+    nb = 2 * size * size + 4 * size + 8 * size
+    fb = 4 * size * size + 4 * size + 8 * size
+    for acc_name, acc in (("f32", 0), ("comp", 1), ("f64combine", 2)):
+        def cg(i, acc=acc):
+            assert lib.lift_gemv_ex(size, size, alpha, L.LIFT_BF16, Ad.data_ptr(), size, xd.data_ptr(), beta,
+                                    yd.data_ptr(), acc, None, sh) == 0
+        rec(f"gemv_bf16_{acc_name}_{size}", _time_calls(cg, 1, stream, reps=20), nb, fb)
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * lift.h -- C ABI of the MI355X (gfx950) map/reduce BLAS library.
+ *
+ * The operations are the linear-algebra programs of Steuwer, Fensch and
+ * Dubach, "Patterns and Rewrite Rules for Systematic Code Generation"
+ * (arXiv 1502.02389), Section 5.1 and its BLAS figure (Fig. 5):
+ *
+ *   scal(a, x)          = map(mult(a), x)
+ *   asum(x)             = reduce(add, 0) . map(abs, x)
+ *   dot(x, y)           = reduce(add, 0) . map(mult) . zip(x, y)
+ *   gemv(A, x, y, a, b) : z = map(scal(a) . dot(x), A);
+ *                         y' = map(add) . zip(z, scal(b, y))      (y = aAx + by)
+ *
+ * Each call runs hand-written HIP kernels for gfx950; nothing runs on the
+ * host but argument checks and launch set-up.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.   Every array pointer is a DEVICE pointer (hipMalloc'd or any
+ *             allocation the device can address), aligned to its element
+ *             size.  Other alignment is not required: misaligned heads and
+ *             tails are handled inside the kernels.  The caller owns every
+ *             buffer; the library keeps no pointer after a call returns.
+ * Sizes.      int64_t element counts; negative sizes are rejected.  An empty
+ *             reduction (n == 0) writes 0, as reduce of the empty array is
+ *             [z] (Table 1); scal with n == 0 and gemv with m == 0 do nothing;
+ *             gemv with n == 0 computes y = b*y.
+ * Streams.    Work is enqueued on `stream` (0 = the null stream) and the call
+ *             returns without synchronising.  Results are valid once the
+ *             stream has reached the call.  No call allocates memory, copies
+ *             to or from the host, or records a memset, so every call can be
+ *             captured into a HIP graph.
+ * Results.    A reduction writes its scalar to DEVICE memory (`result`): the
+ *             paper's reduce returns a one-element array, T[] -> T[1].
+ * Workspace.  asum and dot take a device workspace `ws` of `ws_bytes` bytes,
+ *             at least lift_workspace_bytes().  It must be zero-filled ONCE
+ *             before its first use; every call leaves it zeroed again (the
+ *             last work-group resets the counter it uses), so replays need
+ *             no memset.  Calls that may run concurrently (different streams)
+ *             need different workspaces.
+ * Errors.     Arguments are checked before any HIP call.  LIFT_EINVAL: bad
+ *             size, null pointer with a non-empty extent, pointer not aligned
+ *             to its element size, partial overlap of an output with an
+ *             input, unknown enum or knob value.  LIFT_EWORKSPACE: ws too
+ *             small or null.  LIFT_EHIP: a HIP runtime call failed; its code
+ *             is in lift_last_hip_error().  Nothing is enqueued on error.
+ * Determinism. For a given size, pointer alignment and knob set, the work
+ *             partition and every summation order are fixed, so results are
+ *             bitwise reproducible run to run.  Different knobs associate the
+ *             floating-point sums differently (the paper's reduction rule,
+ *             Fig. 3d, allows any partition); integer-valued inputs whose
+ *             partial sums stay below 2^24 in magnitude give identical
+ *             results under every knob set.
+ */
+#ifndef LIFT_H
+#define LIFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lift_status {
+    LIFT_OK = 0,
+    LIFT_EINVAL = -1,
+    LIFT_EWORKSPACE = -2,
+    LIFT_EHIP = -3,
+    LIFT_EUNSUPPORTED = -4
+} lift_status;
+
+/* Storage / result types. */
+typedef enum lift_dtype {
+    LIFT_F32 = 0,   /* IEEE binary32 */
+    LIFT_BF16 = 1,  /* bfloat16: the upper 16 bits of a binary32 */
+    LIFT_F16 = 2,   /* IEEE binary16 */
+    LIFT_F64 = 3    /* IEEE binary64 (reduction results only) */
+} lift_dtype;
+
+/* Accumulation variants for 16-bit and 32-bit storage. */
+typedef enum lift_acc {
+    LIFT_ACC_F32 = 0,           /* binary32 accumulation everywhere */
+    LIFT_ACC_F32_COMP = 1,      /* compensated binary32: every partial sum is
+                                   a (sum, error) pair propagated with the
+                                   error-free TwoSum transformation */
+    LIFT_ACC_F32_F64COMBINE = 2 /* binary32 within a work-group, binary64 for
+                                   the final cross-work-group combine (gemv:
+                                   for the cross-lane combine of each row) */
+} lift_acc;
+
+/* Launch knobs: the parameters the paper's low-level expressions expose
+ * (split factor, work-group size, vector width; Fig. 9 and Section 6.2)
+ * plus the rows handled together by one wavefront in gemv.  A zero field
+ * selects the library default for that field. */
+typedef struct lift_knobs {
+    int32_t block;         /* work-group size: 64, 128, 256, 512 or 1024 */
+    int32_t vec_bytes;     /* bytes per lane per load: 2 (16-bit storage
+                              only), 4, 8 or 16 -- asVector width times the
+                              element size */
+    int32_t unroll;        /* independent loads in flight per lane: 1, 2, 4, 8 */
+    int32_t rows_per_wave; /* gemv only: 1, 2 or 4 rows per wavefront */
+    int64_t split;         /* elements per work-group chunk (split^n); the
+                              library rounds it up to a whole number of
+                              block * unroll loads and caps the grid at
+                              lift_max_workgroups() */
+} lift_knobs;
+
+/* ---- plain FP32 forms (Fig. 5) --------------------------------------- */
+
+/* scal: out[i] = alpha * x[i], one binary32 multiply per element (rounded
+ * to nearest even), i in [0, n).  `out` may equal `x` (in place); any other
+ * overlap is LIFT_EINVAL. */
+lift_status lift_scal(int64_t n, float alpha, const float *x, float *out, hipStream_t stream);
+
+/* asum: *result = sum_i |x_i| in binary32 (binary32 accumulation). */
+lift_status lift_asum(int64_t n, const float *x, float *result, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* dot: *result = sum_i x_i * y_i in binary32 (products fused into the
+ * accumulation with fma). */
+lift_status lift_dot(int64_t n, const float *x, const float *y, float *result, void *ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+/* gemv: y[i] = alpha * (sum_j A[i*lda + j] * x[j]) + beta * y[i] for
+ * i in [0, m), j in [0, n).  A is row-major (the paper maps the dot over the
+ * rows of A) with leading dimension lda >= max(1, n).  alpha multiplies the
+ * finished dot once.  beta == 0 follows the BLAS convention: y is written
+ * but not read (NaN in y does not propagate).  y must not overlap A or x. */
+lift_status lift_gemv(int64_t m, int64_t n, float alpha, const float *A, int64_t lda,
+                      const float *x, float beta, float *y, hipStream_t stream);
+
+/* Bytes of workspace any asum/dot call (plain or _ex) needs on this device. */
+size_t lift_workspace_bytes(void);
+
+/* Largest work-group count a reduction grid uses. */
+int32_t lift_max_workgroups(void);
+
+/* ---- storage / accumulation variants and explicit knobs -------------- */
+
+/* scal with explicit knobs (NULL = defaults). */
+lift_status lift_scal_ex(int64_t n, float alpha, const float *x, float *out,
+                         const lift_knobs *knobs, hipStream_t stream);
+
+/* asum of x stored as xt (F32, BF16 or F16) with accumulation `acc`; the
+ * result is written as rt (F32 or F64) to device memory. */
+lift_status lift_asum_ex(int64_t n, lift_dtype xt, const void *x, lift_acc acc, lift_dtype rt,
+                         void *result, void *ws, size_t ws_bytes, const lift_knobs *knobs,
+                         hipStream_t stream);
+
+/* dot of x and y, both stored as xt (F32, BF16 or F16); 16-bit products
+ * are exact in binary32. */
+lift_status lift_dot_ex(int64_t n, lift_dtype xt, const void *x, const void *y, lift_acc acc,
+                        lift_dtype rt, void *result, void *ws, size_t ws_bytes,
+                        const lift_knobs *knobs, hipStream_t stream);
+
+/* gemv with A stored as at (F32, BF16 or F16); x and y are binary32. */
+lift_status lift_gemv_ex(int64_t m, int64_t n, float alpha, lift_dtype at, const void *A,
+                         int64_t lda, const float *x, float beta, float *y, lift_acc acc,
+                         const lift_knobs *knobs, hipStream_t stream);
+
+/* ---- diagnostics ------------------------------------------------------ */
+
+/* Static description of a status code. */
+const char *lift_status_string(lift_status status);
+
+/* hipError_t of the last failed HIP call on this thread (0 if none). */
+int lift_last_hip_error(void);
+
+/* Library version, e.g. "lift-mi355x 0.1 gfx950". */
+const char *lift_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIFT_H */

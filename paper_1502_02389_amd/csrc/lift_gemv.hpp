@@ -1,0 +1,241 @@
+// gemv: y = alpha * A x + beta * y, row-major A.
+//
+// The paper's program maps scal(alpha) o dot(x) over the rows of A and then
+// zips the result with scal(beta, y) (Fig. 5).  Here one wavefront owns R
+// rows at a time (map over rows -> map-wavefront); inside a row the 64 lanes
+// read consecutive VB-byte vectors (reorder-stride: lane l takes vectors
+// l, l+64, ...), each lane folds its products with reduce-seq, and a DPP
+// butterfly (iterate of part-red) yields the row's dot.  The R rows of a
+// wavefront share every x load, which divides x traffic by R.  alpha scales
+// the finished dot once, and the zip with beta*y is fused into the store.
+#pragma once
+
+#include "lift_device.hpp"
+#include "lift_internal.hpp"
+
+namespace lift {
+
+// E consecutive binary32 values of x starting at element E * v.
+template <int E>
+__device__ __forceinline__ void load_x(const float *x, int64_t v, float *o)
+{
+    if constexpr (E == 1) {
+        o[0] = x[v];
+    } else if constexpr (E == 2) {
+        u32x2 w = load_vec<8>(x, v);
+        o[0] = bits_to_float(w[0]);
+        o[1] = bits_to_float(w[1]);
+    } else {
+#pragma unroll
+        for (int h = 0; h < E / 4; ++h) {
+            u32x4 w = load_vec<16>(x, v * (E / 4) + h);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                o[4 * h + i] = bits_to_float(w[i]);
+        }
+    }
+}
+
+template <int ACC, int E>
+struct RowAcc;
+
+template <int E>
+struct RowAcc<ACC_F32, E> {
+    float s[E];
+    __device__ __forceinline__ RowAcc()
+    {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            s[e] = 0.f;
+    }
+    __device__ __forceinline__ void add(const float *a, const float *x)
+    {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            s[e] = fmaf(a[e], x[e], s[e]);
+    }
+    __device__ __forceinline__ void add_scalar(float a, float x) { s[0] = fmaf(a, x, s[0]); }
+    __device__ __forceinline__ float value() const
+    {
+        float t[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            t[e] = s[e];
+#pragma unroll
+        for (int w = 1; w < E; w <<= 1)
+#pragma unroll
+            for (int e = 0; e + w < E; e += 2 * w)
+                t[e] = t[e] + t[e + w];
+        return t[0];
+    }
+};
+
+template <int E>
+struct RowAcc<ACC_F64, E> : RowAcc<ACC_F32, E> {};
+
+// Compensated: products split exactly into a*x = q + r (TwoProduct via fma),
+// q summed pairwise per load and added with TwoSum, r into the error term.
+template <int E>
+struct RowAcc<ACC_COMP, E> {
+    Pair p{0.f, 0.f};
+    __device__ __forceinline__ void add(const float *a, const float *x)
+    {
+        float q[E], r[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            q[e] = a[e] * x[e];
+            r[e] = fmaf(a[e], x[e], -q[e]);
+        }
+#pragma unroll
+        for (int w = 1; w < E; w <<= 1)
+#pragma unroll
+            for (int e = 0; e + w < E; e += 2 * w) {
+                q[e] = q[e] + q[e + w];
+                r[e] = r[e] + r[e + w];
+            }
+        p = pair_add(p, q[0]);
+        p.c += r[0];
+    }
+    __device__ __forceinline__ void add_scalar(float a, float x)
+    {
+        float q = a * x;
+        p = pair_add(p, q);
+        p.c += fmaf(a, x, -q);
+    }
+    __device__ __forceinline__ Pair value() const { return p; }
+};
+
+template <int ACC>
+__device__ __forceinline__ void store_row(float *y, int64_t i, float alpha, float beta, float dotv)
+{
+    float by = beta == 0.f ? 0.f : beta * y[i];
+    y[i] = fmaf(alpha, dotv, by);
+}
+
+template <class T, int ACC, int VB, int R, int U>
+__global__ void __launch_bounds__(1024) gemv_kernel(GemvArgs a)
+{
+    constexpr int E = Elems<T, VB>::value;
+    using V = typename Vec<VB>::type;
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = blockDim.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * wpb;
+    const int64_t row_bytes = a.lda * T::bytes;
+    const int64_t tail0 = a.nvec * E;
+
+    for (int64_t r0 = gw * R; r0 < a.m; r0 += nw * R) {  // wave-uniform loop
+        const char *rows[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            rows[r] = reinterpret_cast<const char *>(a.A) + min(r0 + r, a.m - 1) * row_bytes;
+
+        RowAcc<ACC, E> acc[R];
+        int64_t base = 0;
+        for (; base + 64 * U <= a.nvec; base += 64 * U) {
+            float xf[U][E];
+            V va[R][U];
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                load_x<E>(a.x, base + lane + 64 * k, xf[k]);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    va[r][k] = load_vec<VB>(rows[r], base + lane + 64 * k);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    float af[E];
+                    decode<T, VB>(va[r][k], af);
+                    acc[r].add(af, xf[k]);
+                }
+        }
+        for (int64_t v = base + lane; v < a.nvec; v += 64) {
+            float xf[E];
+            load_x<E>(a.x, v, xf);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float af[E];
+                decode<T, VB>(load_vec<VB>(rows[r], v), af);
+                acc[r].add(af, xf);
+            }
+        }
+        if (tail0 + lane < a.n) {  // fewer than E trailing columns
+            float xs = a.x[tail0 + lane];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                acc[r].add_scalar(load_elem<T>(rows[r], tail0 + lane), xs);
+        }
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (ACC == ACC_F64) {
+                double d = wave_sum((double)acc[r].value());
+                if (lane == 0 && r0 + r < a.m) {
+                    double by = a.beta == 0.f ? 0.0 : (double)a.beta * (double)a.y[r0 + r];
+                    a.y[r0 + r] = (float)((double)a.alpha * d + by);
+                }
+            } else if constexpr (ACC == ACC_COMP) {
+                Pair p = wave_sum(acc[r].value());
+                if (lane == 0 && r0 + r < a.m)
+                    store_row<ACC>(a.y, r0 + r, a.alpha, a.beta, p.s + p.c);
+            } else {
+                float d = wave_sum(acc[r].value());
+                if (lane == 0 && r0 + r < a.m)
+                    store_row<ACC>(a.y, r0 + r, a.alpha, a.beta, d);
+            }
+        }
+    }
+}
+
+template <class T, int ACC, int VB, int R>
+const void *gemv_pick_unroll(int unroll)
+{
+    switch (unroll) {
+    case 1: return reinterpret_cast<const void *>(&gemv_kernel<T, ACC, VB, R, 1>);
+    case 2: return reinterpret_cast<const void *>(&gemv_kernel<T, ACC, VB, R, 2>);
+    case 4: return reinterpret_cast<const void *>(&gemv_kernel<T, ACC, VB, R, 4>);
+    default: return nullptr;
+    }
+}
+
+template <class T, int ACC, int VB>
+const void *gemv_pick_rows(int rows, int unroll)
+{
+    switch (rows) {
+    case 1: return gemv_pick_unroll<T, ACC, VB, 1>(unroll);
+    case 2: return gemv_pick_unroll<T, ACC, VB, 2>(unroll);
+    case 4: return gemv_pick_unroll<T, ACC, VB, 4>(unroll);
+    default: return nullptr;
+    }
+}
+
+template <class T, int ACC>
+const void *gemv_pick_vec(int vec_bytes, int rows, int unroll)
+{
+    switch (vec_bytes) {
+    case 2:
+        if constexpr (T::bytes == 2)
+            return gemv_pick_rows<T, ACC, 2>(rows, unroll);
+        return nullptr;
+    case 4: return gemv_pick_rows<T, ACC, 4>(rows, unroll);
+    case 8: return gemv_pick_rows<T, ACC, 8>(rows, unroll);
+    case 16: return gemv_pick_rows<T, ACC, 16>(rows, unroll);
+    default: return nullptr;
+    }
+}
+
+template <class T>
+const void *pick_gemv(int acc, int vec_bytes, int rows, int unroll)
+{
+    switch (acc) {
+    case ACC_F32: return gemv_pick_vec<T, ACC_F32>(vec_bytes, rows, unroll);
+    case ACC_COMP: return gemv_pick_vec<T, ACC_COMP>(vec_bytes, rows, unroll);
+    case ACC_F64: return gemv_pick_vec<T, ACC_F64>(vec_bytes, rows, unroll);
+    default: return nullptr;
+    }
+}
+
+}  // namespace lift

@@ -1,0 +1,11 @@
+// gemv kernels for F16 storage of A (instantiations of lift_gemv.hpp).
+#include "lift_gemv.hpp"
+
+namespace lift {
+
+const void *gemv_kernel_f16(int acc, int vec_bytes, int rows, int unroll)
+{
+    return pick_gemv<F16>(acc, vec_bytes, rows, unroll);
+}
+
+}  // namespace lift

@@ -1,0 +1,11 @@
+// gemv kernels for F32 storage of A (instantiations of lift_gemv.hpp).
+#include "lift_gemv.hpp"
+
+namespace lift {
+
+const void *gemv_kernel_f32(int acc, int vec_bytes, int rows, int unroll)
+{
+    return pick_gemv<F32>(acc, vec_bytes, rows, unroll);
+}
+
+}  // namespace lift

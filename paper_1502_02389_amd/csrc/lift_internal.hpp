@@ -1,0 +1,74 @@
+// Launch descriptors and kernel tables shared by the host library and the
+// kernel translation units.  Host code fills one descriptor per call and
+// launches the table entry chosen by the knobs.
+#pragma once
+
+#include <stdint.h>
+
+namespace lift {
+
+enum Dtype { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2, DT_F64 = 3 };
+enum Op { OP_ASUM = 0, OP_DOT = 1 };
+enum Acc { ACC_F32 = 0, ACC_COMP = 1, ACC_F64 = 2 };
+
+// Workspace layout: a 32-bit arrival counter in the first 256 bytes, then
+// one 16-byte partial slot per work-group.
+constexpr int64_t WS_HEADER = 256;
+constexpr int64_t WS_SLOT = 16;
+constexpr int32_t MAX_WORKGROUPS = 8192;
+
+// reduce(add, 0) . map(abs) over x, or reduce(add, 0) . map(mult) . zip(x, y).
+// Elements [0, head) are scalars before the first VB-aligned address; then
+// nvec aligned vectors; then the scalar tail [head + nvec * E, n).  Work-group
+// b owns vectors [b * chunk, min((b + 1) * chunk, nvec)).
+struct ReduceArgs {
+    const void *x;
+    const void *y;
+    int64_t n;
+    int64_t head;
+    int64_t nvec;
+    int64_t chunk;
+    void *ws;          // header + partial slots (unused when the grid is 1)
+    void *result;
+    int32_t result_f64;
+};
+
+// map(mult(alpha), x) with the same head / vector / tail split.
+struct ScalArgs {
+    const float *x;
+    float *out;
+    int64_t n;
+    int64_t head;
+    int64_t nvec;
+    int64_t chunk;
+    float alpha;
+};
+
+// y = alpha * A x + beta * y; rows are handled R at a time by one wavefront;
+// each row has nvec aligned vectors followed by n - nvec * E scalar columns.
+struct GemvArgs {
+    const void *A;
+    const float *x;
+    float *y;
+    int64_t m;
+    int64_t n;
+    int64_t lda;
+    int64_t nvec;
+    float alpha;
+    float beta;
+};
+
+// Kernel tables (nullptr where a combination is not built).
+const void *reduce_kernel(int dtype, int op, int acc, int vec_bytes, int unroll);
+const void *scal_kernel(int vec_bytes, int unroll);
+const void *gemv_kernel(int dtype, int acc, int vec_bytes, int rows, int unroll);
+
+// Per-dtype tables, one per translation unit.
+const void *reduce_kernel_f32(int op, int acc, int vec_bytes, int unroll);
+const void *reduce_kernel_bf16(int op, int acc, int vec_bytes, int unroll);
+const void *reduce_kernel_f16(int op, int acc, int vec_bytes, int unroll);
+const void *gemv_kernel_f32(int acc, int vec_bytes, int rows, int unroll);
+const void *gemv_kernel_bf16(int acc, int vec_bytes, int rows, int unroll);
+const void *gemv_kernel_f16(int acc, int vec_bytes, int rows, int unroll);
+
+}  // namespace lift

@@ -1,0 +1,338 @@
+// asum and dot: one streaming pass, one launch.
+//
+// The kernel is the paper's fused reduction (the asum derivation of Fig. 8,
+// eq. 8, and the GPU expressions of Fig. 9) laid out for CDNA4:
+//
+//   reduce-seq o join o map-workgroup(
+//       toGlobal(...)                              partial -> workspace slot
+//     o iterate(part-red) with toLocal             DPP wave butterfly + LDS
+//     o map-local(reduce-seq(lambda acc, a: acc + term(a), 0))
+//     o split o reorder-stride                     lane t reads vector t, t+B, ..
+//   ) o asVector o split^chunk                      dwordx4 loads, chunk per WG
+//
+// term(a) = |a| (asum) or a_x * a_y (dot, zip fused into the load).  The
+// final reduce-seq o join runs in the same launch: every work-group stores
+// its partial, then takes a ticket from an agent-scope counter; the one that
+// draws the last ticket folds all partials in work-group order and writes
+// the result, then resets the counter for the next call.  No float atomics
+// and no inter-work-group waiting, so the result is deterministic and the
+// grid always drains.
+#pragma once
+
+#include "lift_device.hpp"
+#include "lift_internal.hpp"
+
+namespace lift {
+
+// Per-lane accumulator of the streaming phase.
+template <int ACC, int E>
+struct LaneAcc;
+
+// binary32: E independent sums (one per vector component), folded pairwise
+// at the end.
+template <int E>
+struct LaneAcc<ACC_F32, E> {
+    float s[E];
+    __device__ __forceinline__ LaneAcc()
+    {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            s[e] = 0.f;
+    }
+    // asum / dot-with-product-given
+    __device__ __forceinline__ void add_terms(const float *t)
+    {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            s[e] += t[e];
+    }
+    __device__ __forceinline__ void add_products(const float *a, const float *b)
+    {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            s[e] = fmaf(a[e], b[e], s[e]);
+    }
+    __device__ __forceinline__ void add_scalar(float v) { s[0] += v; }
+    __device__ __forceinline__ void add_scalar_product(float a, float b) { s[0] = fmaf(a, b, s[0]); }
+    __device__ __forceinline__ float value() const
+    {
+        float t[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            t[e] = s[e];
+#pragma unroll
+        for (int w = 1; w < E; w <<= 1)
+#pragma unroll
+            for (int e = 0; e + w < E; e += 2 * w)
+                t[e] = t[e] + t[e + w];
+        return t[0];
+    }
+};
+
+// binary32 with a binary64 cross-work-group combine: same lane arithmetic.
+template <int E>
+struct LaneAcc<ACC_F64, E> : LaneAcc<ACC_F32, E> {};
+
+// Compensated: the E terms of one load are summed pairwise, then added to
+// the lane's (sum, error) pair with TwoSum; binary32 products contribute
+// their exact rounding error (fma(a, b, -a*b), the TwoProduct of Ogita,
+// Rump and Oishi) to the error term.
+template <int E>
+struct LaneAcc<ACC_COMP, E> {
+    Pair p{0.f, 0.f};
+    __device__ __forceinline__ static float tree(float *t)
+    {
+#pragma unroll
+        for (int w = 1; w < E; w <<= 1)
+#pragma unroll
+            for (int e = 0; e + w < E; e += 2 * w)
+                t[e] = t[e] + t[e + w];
+        return t[0];
+    }
+    __device__ __forceinline__ void add_terms(const float *t)
+    {
+        float u[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            u[e] = t[e];
+        p = pair_add(p, tree(u));
+    }
+    template <bool EXACT_PRODUCTS>
+    __device__ __forceinline__ void add_products_c(const float *a, const float *b)
+    {
+        float q[E], r[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            q[e] = a[e] * b[e];
+            r[e] = EXACT_PRODUCTS ? 0.f : fmaf(a[e], b[e], -q[e]);
+        }
+        p = pair_add(p, tree(q));
+        if (!EXACT_PRODUCTS)
+            p.c += tree(r);
+    }
+    __device__ __forceinline__ void add_scalar(float v) { p = pair_add(p, v); }
+    template <bool EXACT_PRODUCTS>
+    __device__ __forceinline__ void add_scalar_product_c(float a, float b)
+    {
+        float q = a * b;
+        p = pair_add(p, q);
+        if (!EXACT_PRODUCTS)
+            p.c += fmaf(a, b, -q);
+    }
+    __device__ __forceinline__ Pair value() const { return p; }
+};
+
+// Partial slot type written by each work-group.
+template <int ACC> struct SlotT { using type = float; };
+template <> struct SlotT<ACC_COMP> { using type = Pair; };
+template <> struct SlotT<ACC_F64> { using type = double; };
+
+template <int ACC> struct BlockT { using type = float; };
+template <> struct BlockT<ACC_COMP> { using type = Pair; };
+
+__device__ __forceinline__ double to_f64(float v) { return (double)v; }
+__device__ __forceinline__ double to_f64(double v) { return v; }
+__device__ __forceinline__ double to_f64(Pair p) { return (double)p.s + (double)p.c; }
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(double v) { return (float)v; }
+__device__ __forceinline__ float to_f32(Pair p) { return p.s + p.c; }
+
+template <int ACC>
+__device__ __forceinline__ typename SlotT<ACC>::type to_slot(typename BlockT<ACC>::type v)
+{
+    return typename SlotT<ACC>::type(v);
+}
+template <>
+__device__ __forceinline__ Pair to_slot<ACC_COMP>(Pair v)
+{
+    return v;
+}
+
+template <class S>
+__device__ __forceinline__ S zero_of();
+template <> __device__ __forceinline__ float zero_of<float>() { return 0.f; }
+template <> __device__ __forceinline__ double zero_of<double>() { return 0.0; }
+template <> __device__ __forceinline__ Pair zero_of<Pair>() { return Pair{0.f, 0.f}; }
+
+template <class S>
+__device__ __forceinline__ void write_result(void *result, int f64, S v)
+{
+    if (f64)
+        *reinterpret_cast<double *>(result) = to_f64(v);
+    else
+        *reinterpret_cast<float *>(result) = to_f32(v);
+}
+
+// 16-bit products are exact in binary32 (8- or 11-bit significands).
+template <class T> struct ExactProducts { static constexpr bool value = T::bytes == 2; };
+
+template <class T, int OP, int ACC, int E>
+__device__ __forceinline__ void accumulate(LaneAcc<ACC, E> &acc, const float *a, const float *b)
+{
+    if constexpr (OP == OP_ASUM) {
+        float t[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            t[e] = fabsf(a[e]);
+        acc.add_terms(t);
+    } else if constexpr (ACC == ACC_COMP) {
+        acc.template add_products_c<ExactProducts<T>::value>(a, b);
+    } else {
+        acc.add_products(a, b);
+    }
+}
+
+template <class T, int OP, int ACC, int E>
+__device__ __forceinline__ void accumulate_scalar(LaneAcc<ACC, E> &acc, float a, float b)
+{
+    if constexpr (OP == OP_ASUM) {
+        acc.add_scalar(fabsf(a));
+    } else if constexpr (ACC == ACC_COMP) {
+        acc.template add_scalar_product_c<ExactProducts<T>::value>(a, b);
+    } else {
+        acc.add_scalar_product(a, b);
+    }
+}
+
+template <class T, int OP, int ACC, int VB, int U>
+__global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
+{
+    constexpr int E = Elems<T, VB>::value;
+    using V = typename Vec<VB>::type;
+    using BT = typename BlockT<ACC>::type;
+    using ST = typename SlotT<ACC>::type;
+    __shared__ BT lds_block[16];
+    __shared__ ST lds_final[16];
+    __shared__ int last;
+
+    const int t = threadIdx.x;
+    const int64_t B = blockDim.x;
+    const char *xv = reinterpret_cast<const char *>(a.x) + a.head * T::bytes;
+    const char *yv = OP == OP_DOT ? reinterpret_cast<const char *>(a.y) + a.head * T::bytes : nullptr;
+
+    const int64_t vbeg = (int64_t)blockIdx.x * a.chunk;
+    const int64_t vend = min(vbeg + a.chunk, a.nvec);
+    const int64_t step = B * U;
+
+    LaneAcc<ACC, E> acc;
+    int64_t base = vbeg;
+    // full steps: U independent loads per lane (per operand) in flight
+    for (; base + step <= vend; base += step) {
+        V vx[U], vy[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            vx[k] = load_vec<VB>(xv, base + t + k * B);
+            if constexpr (OP == OP_DOT)
+                vy[k] = load_vec<VB>(yv, base + t + k * B);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            float fx[E], fy[E];
+            decode<T, VB>(vx[k], fx);
+            if constexpr (OP == OP_DOT)
+                decode<T, VB>(vy[k], fy);
+            accumulate<T, OP, ACC, E>(acc, fx, fy);
+        }
+    }
+    // the last, partial step of this work-group
+    for (int64_t i = base + t; i < vend; i += B) {
+        float fx[E], fy[E];
+        decode<T, VB>(load_vec<VB>(xv, i), fx);
+        if constexpr (OP == OP_DOT)
+            decode<T, VB>(load_vec<VB>(yv, i), fy);
+        accumulate<T, OP, ACC, E>(acc, fx, fy);
+    }
+    // scalar head (work-group 0) and tail (last work-group), fewer than E each
+    if (blockIdx.x == 0 && t < a.head) {
+        float fy = OP == OP_DOT ? load_elem<T>(a.y, t) : 0.f;
+        accumulate_scalar<T, OP, ACC, E>(acc, load_elem<T>(a.x, t), fy);
+    }
+    const int64_t tail0 = a.head + a.nvec * E;
+    if (blockIdx.x == gridDim.x - 1 && t < a.n - tail0) {
+        float fy = OP == OP_DOT ? load_elem<T>(a.y, tail0 + t) : 0.f;
+        accumulate_scalar<T, OP, ACC, E>(acc, load_elem<T>(a.x, tail0 + t), fy);
+    }
+
+    BT wg = block_sum<BT>(acc.value(), lds_block);
+
+    if (gridDim.x == 1) {
+        if (t == 0)
+            write_result(a.result, a.result_f64, wg);
+        return;
+    }
+
+    unsigned *ticket = reinterpret_cast<unsigned *>(a.ws);
+    ST *slots = reinterpret_cast<ST *>(reinterpret_cast<char *>(a.ws) + WS_HEADER);
+    if (t == 0) {
+        // slot stride is 16 bytes whatever the slot type
+        *reinterpret_cast<ST *>(reinterpret_cast<char *>(slots) + (int64_t)blockIdx.x * WS_SLOT) =
+            to_slot<ACC>(wg);
+        __threadfence();  // release the partial at agent scope (all XCDs)
+        unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last)
+        return;
+
+    __threadfence();  // acquire: every partial is visible from here on
+    ST v = zero_of<ST>();
+    for (int64_t i = t; i < gridDim.x; i += B)
+        v = merge(v, *reinterpret_cast<const ST *>(reinterpret_cast<const char *>(slots) + i * WS_SLOT));
+    v = block_sum<ST>(v, lds_final);
+    if (t == 0) {
+        write_result(a.result, a.result_f64, v);
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Table of instantiated reduce kernels for storage T.
+template <class T, int OP, int ACC, int VB>
+const void *pick_unroll(int unroll)
+{
+    switch (unroll) {
+    case 1: return reinterpret_cast<const void *>(&reduce_kernel<T, OP, ACC, VB, 1>);
+    case 2: return reinterpret_cast<const void *>(&reduce_kernel<T, OP, ACC, VB, 2>);
+    case 4: return reinterpret_cast<const void *>(&reduce_kernel<T, OP, ACC, VB, 4>);
+    case 8: return reinterpret_cast<const void *>(&reduce_kernel<T, OP, ACC, VB, 8>);
+    default: return nullptr;
+    }
+}
+
+template <class T, int OP, int ACC>
+const void *pick_vec(int vec_bytes, int unroll)
+{
+    switch (vec_bytes) {
+    case 2:
+        if constexpr (T::bytes == 2)
+            return pick_unroll<T, OP, ACC, 2>(unroll);
+        return nullptr;
+    case 4: return pick_unroll<T, OP, ACC, 4>(unroll);
+    case 8: return pick_unroll<T, OP, ACC, 8>(unroll);
+    case 16: return pick_unroll<T, OP, ACC, 16>(unroll);
+    default: return nullptr;
+    }
+}
+
+template <class T, int OP>
+const void *pick_acc(int acc, int vec_bytes, int unroll)
+{
+    switch (acc) {
+    case ACC_F32: return pick_vec<T, OP, ACC_F32>(vec_bytes, unroll);
+    case ACC_COMP: return pick_vec<T, OP, ACC_COMP>(vec_bytes, unroll);
+    case ACC_F64: return pick_vec<T, OP, ACC_F64>(vec_bytes, unroll);
+    default: return nullptr;
+    }
+}
+
+template <class T>
+const void *pick_reduce(int op, int acc, int vec_bytes, int unroll)
+{
+    if (op == OP_ASUM)
+        return pick_acc<T, OP_ASUM>(acc, vec_bytes, unroll);
+    if (op == OP_DOT)
+        return pick_acc<T, OP_DOT>(acc, vec_bytes, unroll);
+    return nullptr;
+}
+
+}  // namespace lift

@@ -1,0 +1,298 @@
+"""ctypes binding of ``liblift.so`` -- argument marshalling only.
+
+Two layers:
+
+* ``lift_scal``, ``lift_asum``, ... : the C entry points under their own
+  names, taking integers (sizes), floats and raw device addresses, returning
+  the ``lift_status`` code.  Declared in ``include/lift.h``.
+* ``scal``, ``asum``, ``dot``, ``gemv`` : tensor conveniences that check
+  device / dtype / contiguity, allocate outputs and the per-stream workspace
+  with PyTorch, and call the entry points above on the current HIP stream.
+  Every step of the computation runs in the library's kernels; there is no
+  fallback: without the built library these raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblift.so")
+
+LIFT_OK, LIFT_EINVAL, LIFT_EWORKSPACE, LIFT_EHIP, LIFT_EUNSUPPORTED = 0, -1, -2, -3, -4
+LIFT_F32, LIFT_BF16, LIFT_F16, LIFT_F64 = 0, 1, 2, 3
+LIFT_ACC_F32, LIFT_ACC_F32_COMP, LIFT_ACC_F32_F64COMBINE = 0, 1, 2
+
+ACC = {"f32": LIFT_ACC_F32, "comp": LIFT_ACC_F32_COMP, "f64combine": LIFT_ACC_F32_F64COMBINE}
+
+
+class LiftError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = _lib().lift_status_string(status).decode() if _LIB is not None else str(status)
+        extra = ""
+        if status == LIFT_EHIP:
+            extra = f" (hipError {_lib().lift_last_hip_error()})"
+        super().__init__(f"{what}: {msg}{extra} [{status}]")
+
+
+class lift_knobs(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32),
+        ("vec_bytes", ctypes.c_int32),
+        ("unroll", ctypes.c_int32),
+        ("rows_per_wave", ctypes.c_int32),
+        ("split", ctypes.c_int64),
+    ]
+
+
+def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0):
+    return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split)
+
+
+_LIB = None
+_LOCK = threading.Lock()
+
+_i64, _f32, _vp, _sz, _i32 = ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+_kp = ctypes.POINTER(lift_knobs)
+
+SIGNATURES = {
+    "lift_scal": (_i32, [_i64, _f32, _vp, _vp, _vp]),
+    "lift_asum": (_i32, [_i64, _vp, _vp, _vp, _sz, _vp]),
+    "lift_dot": (_i32, [_i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "lift_gemv": (_i32, [_i64, _i64, _f32, _vp, _i64, _vp, _f32, _vp, _vp]),
+    "lift_workspace_bytes": (_sz, []),
+    "lift_max_workgroups": (ctypes.c_int32, []),
+    "lift_scal_ex": (_i32, [_i64, _f32, _vp, _vp, _kp, _vp]),
+    "lift_asum_ex": (_i32, [_i64, _i32, _vp, _i32, _i32, _vp, _vp, _sz, _kp, _vp]),
+    "lift_dot_ex": (_i32, [_i64, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _sz, _kp, _vp]),
+    "lift_gemv_ex": (_i32, [_i64, _i64, _f32, _i32, _vp, _i64, _vp, _f32, _vp, _i32, _kp, _vp]),
+    "lift_status_string": (ctypes.c_char_p, [_i32]),
+    "lift_last_hip_error": (_i32, []),
+    "lift_version": (ctypes.c_char_p, []),
+}
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        with _LOCK:
+            if _LIB is None:
+                if not os.path.exists(LIB_PATH):
+                    raise ImportError(
+                        f"{LIB_PATH} is not built; run `python -m paper_1502_02389_amd.build` "
+                        "(there is no CPU fallback)")
+                lib = ctypes.CDLL(LIB_PATH)
+                for name, (res, args) in SIGNATURES.items():
+                    fn = getattr(lib, name)
+                    fn.restype = res
+                    fn.argtypes = args
+                _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (loads it on first use)."""
+    return _lib()
+
+
+# ---------------------------------------------------------------- C entry points
+
+
+def lift_scal(n, alpha, x, out, stream=0):
+    return _lib().lift_scal(n, alpha, x, out, stream)
+
+
+def lift_asum(n, x, result, ws, ws_bytes, stream=0):
+    return _lib().lift_asum(n, x, result, ws, ws_bytes, stream)
+
+
+def lift_dot(n, x, y, result, ws, ws_bytes, stream=0):
+    return _lib().lift_dot(n, x, y, result, ws, ws_bytes, stream)
+
+
+def lift_gemv(m, n, alpha, A, lda, x, beta, y, stream=0):
+    return _lib().lift_gemv(m, n, alpha, A, lda, x, beta, y, stream)
+
+
+def lift_workspace_bytes():
+    return _lib().lift_workspace_bytes()
+
+
+def lift_max_workgroups():
+    return _lib().lift_max_workgroups()
+
+
+def _kptr(k):
+    return ctypes.byref(k) if k is not None else None
+
+
+def lift_scal_ex(n, alpha, x, out, knobs=None, stream=0):
+    return _lib().lift_scal_ex(n, alpha, x, out, _kptr(knobs), stream)
+
+
+def lift_asum_ex(n, xt, x, acc, rt, result, ws, ws_bytes, knobs=None, stream=0):
+    return _lib().lift_asum_ex(n, xt, x, acc, rt, result, ws, ws_bytes, _kptr(knobs), stream)
+
+
+def lift_dot_ex(n, xt, x, y, acc, rt, result, ws, ws_bytes, knobs=None, stream=0):
+    return _lib().lift_dot_ex(n, xt, x, y, acc, rt, result, ws, ws_bytes, _kptr(knobs), stream)
+
+
+def lift_gemv_ex(m, n, alpha, at, A, lda, x, beta, y, acc, knobs=None, stream=0):
+    return _lib().lift_gemv_ex(m, n, alpha, at, A, lda, x, beta, y, acc, _kptr(knobs), stream)
+
+
+def lift_status_string(status):
+    return _lib().lift_status_string(status).decode()
+
+
+def lift_last_hip_error():
+    return _lib().lift_last_hip_error()
+
+
+def lift_version():
+    return _lib().lift_version().decode()
+
+
+# ---------------------------------------------------------------- tensor layer
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+_WS = {}
+_WS_LOCK = threading.Lock()
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def workspace(device, stream=None):
+    """The zero-initialised workspace for (device, stream), allocated once.
+
+    Every asum/dot call leaves it zeroed again, so it is reused without a
+    memset; concurrent streams get their own.
+    """
+    torch = _torch()
+    device = torch.device(device)
+    handle = _stream_handle(device) if stream is None else stream
+    key = (device.index, handle)
+    with _WS_LOCK:
+        ws = _WS.get(key)
+        if ws is None:
+            ws = torch.zeros(lift_workspace_bytes(), dtype=torch.uint8, device=device)
+            _WS[key] = ws
+    return ws
+
+
+_DT = None
+
+
+def _dtype_code(t):
+    torch = _torch()
+    global _DT
+    if _DT is None:
+        _DT = {torch.float32: LIFT_F32, torch.bfloat16: LIFT_BF16, torch.float16: LIFT_F16,
+               torch.float64: LIFT_F64}
+    try:
+        return _DT[t]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t}") from None
+
+
+def _check_tensor(t, name, dtypes):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU (got {t.device}); there is no CPU path")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _ok(status, what):
+    if status != LIFT_OK:
+        raise LiftError(status, what)
+
+
+def scal(alpha, x, out=None, knobs=None):
+    """out = alpha * x (binary32); ``out`` may be ``x`` for in-place."""
+    torch = _torch()
+    _check_tensor(x, "x", (torch.float32,))
+    if out is None:
+        out = torch.empty_like(x)
+    _check_tensor(out, "out", (torch.float32,))
+    if out.numel() != x.numel():
+        raise ValueError("out must match x")
+    s = _stream_handle(x.device)
+    _ok(lift_scal_ex(x.numel(), float(alpha), x.data_ptr(), out.data_ptr(), knobs, s), "lift_scal")
+    return out
+
+
+def _reduce(which, x, y, acc, result_dtype, knobs):
+    torch = _torch()
+    _check_tensor(x, "x", (torch.float32, torch.bfloat16, torch.float16))
+    if y is not None:
+        _check_tensor(y, "y", (x.dtype,))
+        if y.numel() != x.numel():
+            raise ValueError("x and y must have the same length")
+        if y.device != x.device:
+            raise ValueError("x and y must be on the same device")
+    result = torch.empty((), dtype=result_dtype, device=x.device)
+    ws = workspace(x.device)
+    s = _stream_handle(x.device)
+    accc = ACC[acc] if isinstance(acc, str) else int(acc)
+    rt = _dtype_code(result_dtype)
+    if which == "asum":
+        st = lift_asum_ex(x.numel(), _dtype_code(x.dtype), x.data_ptr(), accc, rt, result.data_ptr(),
+                          ws.data_ptr(), ws.numel(), knobs, s)
+    else:
+        st = lift_dot_ex(x.numel(), _dtype_code(x.dtype), x.data_ptr(), y.data_ptr(), accc, rt,
+                         result.data_ptr(), ws.data_ptr(), ws.numel(), knobs, s)
+    _ok(st, f"lift_{which}")
+    return result
+
+
+def asum(x, acc="f32", result_dtype=None, knobs=None):
+    """sum |x_i| as a 0-d device tensor (binary32 unless result_dtype=float64)."""
+    torch = _torch()
+    return _reduce("asum", x, None, acc, result_dtype or torch.float32, knobs)
+
+
+def dot(x, y, acc="f32", result_dtype=None, knobs=None):
+    """sum x_i y_i as a 0-d device tensor."""
+    torch = _torch()
+    return _reduce("dot", x, y, acc, result_dtype or torch.float32, knobs)
+
+
+def gemv(alpha, A, x, beta, y, acc="f32", knobs=None, lda=None):
+    """y <- alpha * A x + beta * y in place (row-major A, rows of length lda).
+
+    ``A`` is (m, lda) with the matrix in its first n = len(x) columns.
+    """
+    torch = _torch()
+    _check_tensor(A, "A", (torch.float32, torch.bfloat16, torch.float16))
+    _check_tensor(x, "x", (torch.float32,))
+    _check_tensor(y, "y", (torch.float32,))
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    m, n = A.shape[0], x.numel()
+    lda = A.shape[1] if lda is None else lda
+    if A.shape[1] != lda or lda < n:
+        raise ValueError("A must be (m, lda) with lda >= len(x)")
+    if y.numel() != m:
+        raise ValueError("y must have one entry per row of A")
+    s = _stream_handle(A.device)
+    accc = ACC[acc] if isinstance(acc, str) else int(acc)
+    _ok(lift_gemv_ex(m, n, float(alpha), _dtype_code(A.dtype), A.data_ptr(), lda, x.data_ptr(),
+                     float(beta), y.data_ptr(), accc, knobs, s), "lift_gemv")
+    return y

@@ -1,0 +1,159 @@
+"""C ABI contract on the CPU: the library loads, exports every entry point
+declared in include/lift.h, and rejects invalid arguments before any HIP
+call.
+
+The rejection cases pass made-up device addresses that the library must turn
+down during argument checking, so this module is skipped wherever a GPU is
+visible (a broken check would otherwise hand those addresses to a kernel).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1502_02389_amd as L
+from paper_1502_02389_amd import lift as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = open(os.path.join(ROOT, "include", "lift.h")).read()
+
+
+def _gpu_visible():
+    try:
+        import torch
+
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def declared_functions():
+    body = re.sub(r"/\*.*?\*/", "", HEADER, flags=re.S)
+    return sorted(set(re.findall(r"\b(lift_[a-z0-9_]+)\s*\(", body)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ("lift_scal", "lift_asum", "lift_dot", "lift_gemv", "lift_workspace_bytes",
+                 "lift_asum_ex", "lift_dot_ex", "lift_gemv_ex", "lift_scal_ex"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) <= set(B.SIGNATURES)
+    for n in declared_functions():
+        assert hasattr(B, n), n
+
+
+def test_enum_values_match_header():
+    for name, value in [("LIFT_OK", 0), ("LIFT_EINVAL", -1), ("LIFT_EWORKSPACE", -2), ("LIFT_EHIP", -3),
+                        ("LIFT_EUNSUPPORTED", -4), ("LIFT_F32", 0), ("LIFT_BF16", 1), ("LIFT_F16", 2),
+                        ("LIFT_F64", 3), ("LIFT_ACC_F32", 0), ("LIFT_ACC_F32_COMP", 1),
+                        ("LIFT_ACC_F32_F64COMBINE", 2)]:
+        assert re.search(rf"\b{name}\s*=\s*{value}\b", HEADER), name
+        assert getattr(B, name) == value
+
+
+def test_knobs_struct_layout():
+    # int32 x4 then int64: 24 bytes, split at offset 16
+    assert ctypes.sizeof(B.lift_knobs) == 24
+    assert B.lift_knobs.split.offset == 16
+
+
+def test_workspace_size_and_version():
+    assert L.lift_workspace_bytes() >= 256 + 16 * L.lift_max_workgroups()
+    assert L.lift_max_workgroups() >= 1024
+    assert "gfx950" in L.lift_version()
+    assert L.lift_status_string(L.LIFT_EINVAL) == "invalid argument"
+
+
+# ------------------------------------------------------------------ rejections
+
+cpu_only = pytest.mark.skipif(_gpu_visible(), reason="passes fake device addresses; CPU only")
+
+X = 0x7F0000000000          # made-up, 256-byte aligned "device" addresses
+Y = 0x7F0001000000
+R = 0x7F0002000000
+WS = 0x7F0003000000
+WSB = None
+
+
+def wsb():
+    return L.lift_workspace_bytes()
+
+
+@cpu_only
+@pytest.mark.parametrize("case,expect", [
+    (lambda: L.lift_asum(-1, X, R, WS, wsb()), L.LIFT_EINVAL),                 # negative n
+    (lambda: L.lift_asum(10, 0, R, WS, wsb()), L.LIFT_EINVAL),                 # null x
+    (lambda: L.lift_asum(10, X, 0, WS, wsb()), L.LIFT_EINVAL),                 # null result
+    (lambda: L.lift_asum(10, X + 2, R, WS, wsb()), L.LIFT_EINVAL),             # x not 4-aligned
+    (lambda: L.lift_asum(10, X, R + 1, WS, wsb()), L.LIFT_EINVAL),             # result misaligned
+    (lambda: L.lift_asum(10, X, R, 0, wsb()), L.LIFT_EWORKSPACE),              # no workspace
+    (lambda: L.lift_asum(10, X, R, WS, wsb() - 1), L.LIFT_EWORKSPACE),         # too small
+    (lambda: L.lift_asum(10, X, R, WS + 4, wsb()), L.LIFT_EINVAL),             # ws not 16-aligned
+    (lambda: L.lift_asum(10, X, X + 8, WS, wsb()), L.LIFT_EINVAL),             # result inside x
+    (lambda: L.lift_asum(10, X, WS + 64, WS, wsb()), L.LIFT_EINVAL),           # result inside ws
+    (lambda: L.lift_dot(10, X, 0, R, WS, wsb()), L.LIFT_EINVAL),               # null y
+    (lambda: L.lift_dot(10, X, Y + 2, R, WS, wsb()), L.LIFT_EINVAL),           # y misaligned
+    (lambda: L.lift_dot(10, X, Y, Y + 4, WS, wsb()), L.LIFT_EINVAL),           # result inside y
+    (lambda: L.lift_scal(-5, 2.0, X, Y), L.LIFT_EINVAL),
+    (lambda: L.lift_scal(10, 2.0, 0, Y), L.LIFT_EINVAL),
+    (lambda: L.lift_scal(10, 2.0, X, 0), L.LIFT_EINVAL),
+    (lambda: L.lift_scal(10, 2.0, X, X + 4), L.LIFT_EINVAL),                   # partial overlap
+    (lambda: L.lift_scal(10, 2.0, X + 36, X), L.LIFT_EINVAL),                  # partial overlap
+    (lambda: L.lift_gemv(-1, 4, 1.0, X, 4, Y, 0.5, R), L.LIFT_EINVAL),
+    (lambda: L.lift_gemv(4, -1, 1.0, X, 4, Y, 0.5, R), L.LIFT_EINVAL),
+    (lambda: L.lift_gemv(4, 8, 1.0, X, 7, Y, 0.5, R), L.LIFT_EINVAL),          # lda < n
+    (lambda: L.lift_gemv(4, 0, 1.0, X, 0, Y, 0.5, R), L.LIFT_EINVAL),          # lda < 1
+    (lambda: L.lift_gemv(4, 8, 1.0, 0, 8, Y, 0.5, R), L.LIFT_EINVAL),          # null A
+    (lambda: L.lift_gemv(4, 8, 1.0, X, 8, 0, 0.5, R), L.LIFT_EINVAL),          # null x
+    (lambda: L.lift_gemv(4, 8, 1.0, X, 8, Y, 0.5, 0), L.LIFT_EINVAL),          # null y
+    (lambda: L.lift_gemv(4, 8, 1.0, X, 8, Y, 0.5, X + 16), L.LIFT_EINVAL),     # y inside A
+    (lambda: L.lift_gemv(4, 8, 1.0, X, 8, Y, 0.5, Y + 4), L.LIFT_EINVAL),      # y inside x
+    (lambda: L.lift_gemv(4, 8, 1.0, X, 8, Y + 2, 0.5, R), L.LIFT_EINVAL),      # x misaligned
+])
+def test_rejects_before_any_hip_call(case, expect):
+    assert case() == expect
+
+
+@cpu_only
+def test_ex_rejects_bad_enums_and_knobs():
+    w = wsb()
+    assert L.lift_asum_ex(8, 7, X, 0, 0, R, WS, w) == L.LIFT_EINVAL                # dtype
+    assert L.lift_asum_ex(8, L.LIFT_F64, X, 0, 0, R, WS, w) == L.LIFT_EINVAL       # f64 storage
+    assert L.lift_asum_ex(8, 0, X, 9, 0, R, WS, w) == L.LIFT_EINVAL                # acc
+    assert L.lift_asum_ex(8, 0, X, 0, L.LIFT_BF16, R, WS, w) == L.LIFT_EINVAL      # result type
+    assert L.lift_asum_ex(8, 0, X, 0, L.LIFT_F64, R + 4, WS, w) == L.LIFT_EINVAL   # f64 result misaligned
+    assert L.lift_asum_ex(8, L.LIFT_BF16, X + 1, 0, 0, R, WS, w) == L.LIFT_EINVAL  # bf16 misaligned
+    for bad in (B.knobs(block=96), B.knobs(block=2048), B.knobs(block=32), B.knobs(vec_bytes=3),
+                B.knobs(vec_bytes=2), B.knobs(vec_bytes=32), B.knobs(unroll=3), B.knobs(unroll=16),
+                B.knobs(rows_per_wave=8), B.knobs(split=-1)):
+        assert L.lift_asum_ex(8, 0, X, 0, 0, R, WS, w, bad) == L.LIFT_EINVAL
+    assert L.lift_gemv_ex(4, 8, 1.0, 5, X, 8, Y, 0.5, R, 0) == L.LIFT_EINVAL
+    assert L.lift_gemv_ex(4, 8, 1.0, 0, X, 8, Y, 0.5, R, 4) == L.LIFT_EINVAL
+    assert L.lift_scal_ex(8, 1.0, X, Y, B.knobs(unroll=5)) == L.LIFT_EINVAL
+
+
+@cpu_only
+def test_valid_call_without_gpu_reports_hip_error():
+    # all checks pass; the first HIP call fails because no device exists
+    st = L.lift_asum(16, X, R, WS, wsb())
+    assert st == L.LIFT_EHIP
+    assert L.lift_last_hip_error() != 0
+
+
+def test_tensor_layer_refuses_cpu_tensors():
+    import torch
+
+    with pytest.raises(ValueError, match="GPU"):
+        L.asum(torch.ones(4))
+    with pytest.raises(ValueError, match="GPU"):
+        L.scal(2.0, torch.ones(4))

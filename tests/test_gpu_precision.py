@@ -1,0 +1,147 @@
+"""GPU parity of the storage / accumulation variants.
+
+x, y and A stored as bfloat16 or binary16 and accumulated in binary32:
+plain, compensated (TwoSum pairs), and binary64 cross-work-group combine.
+The reference is the binary64 oracle on the STORED values (the 16-bit
+rounding of the inputs is the caller's choice, not an error of the sum).
+Bars: every variant within 1e-5 (the binary32 bar, same measures as the
+fp32 tests); the compensated variant within 1e-6; on an input built to
+defeat a binary32 running sum, the compensated error is far below the
+plain one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1502_02389_amd as L
+import workloads as W
+from tests.gpu_util import banner, o_asum, o_dot, o_gemv, rel
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+ACCS = ["f32", "comp", "f64combine"]
+BOUND = {"f32": 1e-5, "comp": 1e-6, "f64combine": 1e-5}
+
+
+@pytest.fixture(scope="module", params=["bf16", "f16"])
+def vectors(request):
+    storage = request.param
+    x, y = W.config4_vectors(storage)
+    ra = o_asum(x)
+    rd, mass = o_dot(x, y)
+    return storage, x, y, ra, rd, mass
+
+
+@pytest.mark.parametrize("acc", ACCS)
+@pytest.mark.parametrize("rt", [torch.float32, torch.float64])
+def test_config4_asum_dot(gpu_device, vectors, acc, rt):
+    storage, x, y, ra, rd, mass = vectors
+    banner("config4", storage, acc, rt)
+    xd, yd = x.to(DEV), y.to(DEV)
+    ga = L.asum(xd, acc=acc, result_dtype=rt).item()
+    gd = L.dot(xd, yd, acc=acc, result_dtype=rt).item()
+    assert rel(ga, ra) <= BOUND[acc], (ga, ra)
+    assert abs(gd - rd) <= BOUND[acc] * mass, (gd, rd, mass)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("acc", ACCS)
+def test_variants_integer_bitexact_all_vector_widths(gpu_device, storage, acc):
+    n = (1 << 19) + 11
+    g0 = W.gen(600)
+    x = W.integers(n, -8, 8, g0, storage)
+    y = W.integers(n, -4, 4, g0, storage)
+    ra = o_asum(x)
+    rd, _ = o_dot(x, y)
+    widths = (2, 4, 8, 16) if storage != "f32" else (4, 8, 16)
+    for off in (0, 1):
+        xd, yd = x.to(DEV)[off:], y.to(DEV)[off:]
+        ra_o = ra if off == 0 else o_asum(x[off:].contiguous())
+        rd_o = rd if off == 0 else o_dot(x[off:].contiguous(), y[off:].contiguous())[0]
+        for v in widths:
+            for u in (1, 4):
+                k = L.knobs(vec_bytes=v, unroll=u)
+                banner("variant ints", storage, acc, v, u, off)
+                assert L.asum(xd, acc=acc, knobs=k).item() == ra_o
+                assert L.dot(xd, yd, acc=acc, knobs=k).item() == rd_o
+
+
+def test_compensated_beats_plain_on_adversarial_input(gpu_device):
+    n = 1 << 22
+    x = torch.ones(n)
+    x[0] = 2.0 ** 24                # every later 1.0 vanishes in a binary32 running sum next to it
+    r = float(2 ** 24 + n - 1)
+    xd = x.to(DEV)
+    k = L.knobs(block=64, vec_bytes=16, unroll=4, split=n // 16)   # long per-lane runs
+    banner("adversarial")
+    e_plain = rel(L.asum(xd, acc="f32", knobs=k).item(), r)
+    e_comp = rel(L.asum(xd, acc="comp", knobs=k).item(), r)
+    e_comp64 = rel(L.asum(xd, acc="comp", result_dtype=torch.float64, knobs=k).item(), r)
+    assert e_plain > 1e-5
+    assert e_comp <= 1e-7 and e_comp64 <= 1e-7
+    assert e_comp * 100 < e_plain
+
+
+def test_f64combine_result_carries_more_digits(gpu_device):
+    # many work-group partials of different magnitude: binary64 combine with a
+    # binary64 result is at least as close as the binary32 combine
+    x, _ = W.config4_vectors("bf16", n=1 << 24)
+    r = o_asum(x)
+    xd = x.to(DEV)
+    banner("f64 combine")
+    e32 = rel(L.asum(xd, acc="f32").item(), r)
+    e64 = rel(L.asum(xd, acc="f64combine", result_dtype=torch.float64).item(), r)
+    assert e64 <= max(e32, 1e-7)
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_config4_gemv_bf16(gpu_device, acc):
+    A, x, y, alpha, beta = _gemv_operands()
+    banner("config4 gemv bf16", acc)
+    yd = y.to(DEV)
+    L.gemv(alpha, _gemv_dev(A), x.to(DEV), beta, yd, acc=acc)
+    r, mass = _gemv_ref()
+    g = yd.cpu().numpy().astype(np.float64)
+    err = np.abs(g - r) / mass
+    assert float(err.max()) <= BOUND[acc], float(err.max())
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("acc", ACCS)
+def test_gemv_16bit_shapes_and_widths(gpu_device, storage, acc):
+    g0 = W.gen(610)
+    m, n, lda = 97, 1001, 1008
+    A = W.normal((m, lda), g0, storage)
+    x = W.normal(n, g0)
+    y = W.normal(m, g0)
+    r, mass = o_gemv(0.75, A, x, 0.5, y, n)
+    Ad, xd = A.to(DEV), x.to(DEV)
+    for v in (2, 4, 8, 16):
+        for rows in (1, 4):
+            banner("gemv 16-bit", storage, acc, v, rows)
+            yd = y.to(DEV)
+            L.gemv(0.75, Ad, xd, 0.5, yd, acc=acc, lda=lda, knobs=L.knobs(vec_bytes=v, rows_per_wave=rows))
+            err = np.abs(yd.cpu().numpy().astype(np.float64) - r) / mass
+            assert float(err.max()) <= BOUND[acc]
+
+
+_G = {}
+
+
+def _gemv_operands():
+    if "ops" not in _G:
+        _G["ops"] = W.config4_gemv()
+    return _G["ops"]
+
+
+def _gemv_dev(A):
+    if "A" not in _G:
+        _G["A"] = A.to(DEV)
+    return _G["A"]
+
+
+def _gemv_ref():
+    if "ref" not in _G:
+        A, x, y, alpha, beta = _gemv_operands()
+        _G["ref"] = o_gemv(alpha, A, x, beta, y)
+    return _G["ref"]
