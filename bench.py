@@ -204,6 +204,14 @@ def main():
         "kernels": kernels,
     }
 
+    # measured device-copy ceiling: torch's copy kernel, cold, 2 x 64 MiB per call
+    srcs = [s["xs"] for s in sets]
+    dsts = [s["out"] for s in sets]
+    us = _time_calls(lambda i: dsts[i].copy_(srcs[i]), nsets, stream, reps=100)
+    result["copy_ceiling"] = {"kernel": "torch copy_ (device to device)", "avg_us": round(us, 3),
+                              "GB_s": round(8 * n / (us * 1e-6) / 1e9, 1)}
+    log("copy ceiling", result["copy_ceiling"])
+
     # ------------------------------------------------------------ CPU oracle
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(x_cpu, y_cpu, alpha, args.cpu_seconds, sets[0], step_bytes)

@@ -127,11 +127,14 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
     return LIFT_OK;
 }
 
-// Defaults (chosen by measurement on MI355X; see the tuning cache).
-constexpr Knobs DEF_SCAL = {256, 16, 4, 1, 0};
-constexpr Knobs DEF_REDUCE = {256, 16, 4, 1, 0};
-constexpr Knobs DEF_GEMV = {256, 16, 2, 1, 0};
-constexpr int64_t WG_PER_CU_STREAM = 4;  // default grid = this many work-groups per CU
+// Defaults, from the knob search on MI355X (256 CUs): reductions run about
+// one long-lived work-group per CU (fewer partials, shorter combine tail),
+// scal many one-step work-groups, gemv small work-groups of row wavefronts.
+constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0};
+constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0};
+constexpr Knobs DEF_GEMV = {128, 16, 4, 1, 0};
+constexpr int64_t WG_PER_CU_SCAL = 32;    // default grid for scal
+constexpr int64_t WG_PER_CU_REDUCE = 1;   // default grid for asum / dot
 
 // Split a range of n elements of `ebytes` bytes at base address p into a
 // scalar head (up to the first vb-aligned address), whole vb-byte vectors,
@@ -158,14 +161,15 @@ bool split3(const void *p, const void *q, int64_t n, int ebytes, int vb, Split3 
 
 // Vectors per work-group: the requested split (elements) or the default
 // grid, rounded up to whole block * unroll steps, with the grid capped.
-int64_t chunk_for(int64_t nvec, int64_t elems_per_vec, const Knobs &k, int cus, int64_t max_wg)
+int64_t chunk_for(int64_t nvec, int64_t elems_per_vec, const Knobs &k, int cus, int64_t wg_per_cu,
+                  int64_t max_wg)
 {
     const int64_t step = (int64_t)k.block * k.unroll;
     int64_t chunk;
     if (k.split > 0) {
         chunk = (k.split + elems_per_vec - 1) / elems_per_vec;
     } else {
-        int64_t target = (int64_t)cus * WG_PER_CU_STREAM;
+        int64_t target = (int64_t)cus * wg_per_cu;
         chunk = (nvec + target - 1) / std::max<int64_t>(target, 1);
     }
     chunk = std::max<int64_t>(step, (chunk + step - 1) / step * step);
@@ -224,7 +228,10 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
         overlaps(result, rb, ws, (int64_t)ws_bytes))
         return LIFT_EINVAL;
     Knobs k;
-    lift_status st = resolve(knobs, DEF_REDUCE, eb, &k);
+    Knobs def = DEF_REDUCE;
+    if (eb == 2)
+        def.unroll = 4;  // 8 elements per 16-byte load already; more only adds registers
+    lift_status st = resolve(knobs, def, eb, &k);
     if (st != LIFT_OK)
         return st;
 
@@ -244,7 +251,7 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
     if (st != LIFT_OK)
         return st;
     const int64_t e = vb / eb;
-    const int64_t chunk = chunk_for(sp.nvec, e, k, cus, MAX_WORKGROUPS);
+    const int64_t chunk = chunk_for(sp.nvec, e, k, cus, WG_PER_CU_REDUCE, MAX_WORKGROUPS);
     const int64_t grid = std::max<int64_t>(1, (sp.nvec + chunk - 1) / chunk);
 
     ReduceArgs a;
@@ -285,6 +292,8 @@ lift_status gemv_common(int64_t m, int64_t n, float alpha, int at, const void *A
     if (m == 0)
         return LIFT_OK;
 
+    if (!knobs || !knobs->rows_per_wave)
+        k.rows = m * n > ((int64_t)1 << 25) ? 2 : 1;  // long matrices: share x loads over 2 rows
     // Vector path needs every row start and x aligned for the chosen width.
     int vb = k.vec_bytes;
     int64_t e = vb / eb;
@@ -356,7 +365,7 @@ lift_status lift_scal_ex(int64_t n, float alpha, const float *x, float *out, con
     st = cu_count(&cus);
     if (st != LIFT_OK)
         return st;
-    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, INT32_MAX);
+    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, WG_PER_CU_SCAL, INT32_MAX);
     const int64_t grid = std::max<int64_t>(1, (sp.nvec + chunk - 1) / chunk);
     ScalArgs a;
     a.x = x;

@@ -38,6 +38,21 @@ __device__ __forceinline__ typename Vec<VB>::type load_vec(const void *base, int
     return reinterpret_cast<const typename Vec<VB>::type *>(base)[i];
 }
 
+// Streaming load of data read exactly once: the nontemporal hint keeps it
+// from displacing reused lines and measurably raises sustained HBM read
+// bandwidth on gfx950.
+template <int VB>
+__device__ __forceinline__ typename Vec<VB>::type load_stream(const void *base, int64_t i)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const typename Vec<VB>::type *>(base) + i);
+}
+
+template <int VB>
+__device__ __forceinline__ void store_stream(void *base, int64_t i, typename Vec<VB>::type v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<typename Vec<VB>::type *>(base) + i);
+}
+
 __device__ __forceinline__ float bits_to_float(uint32_t b) { return __builtin_bit_cast(float, b); }
 
 // Exact decode of one 32-bit word holding two 16-bit values (lower address

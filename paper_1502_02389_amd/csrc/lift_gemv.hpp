@@ -6,7 +6,8 @@
 // read consecutive VB-byte vectors (reorder-stride: lane l takes vectors
 // l, l+64, ...), each lane folds its products with reduce-seq, and a DPP
 // butterfly (iterate of part-red) yields the row's dot.  The R rows of a
-// wavefront share every x load, which divides x traffic by R.  alpha scales
+// wavefront share every x load, which divides x traffic by R.  A is read
+// once with nontemporal loads; x stays cache-resident.  alpha scales
 // the finished dot once, and the zip with beta*y is fused into the store.
 #pragma once
 
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(1024) gemv_kernel(GemvArgs a)
             for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int k = 0; k < U; ++k)
-                    va[r][k] = load_vec<VB>(rows[r], base + lane + 64 * k);
+                    va[r][k] = load_stream<VB>(rows[r], base + lane + 64 * k);
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(1024) gemv_kernel(GemvArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 float af[E];
-                decode<T, VB>(load_vec<VB>(rows[r], v), af);
+                decode<T, VB>(load_stream<VB>(rows[r], v), af);
                 acc[r].add(af, xf);
             }
         }

@@ -17,6 +17,13 @@
 // the result, then resets the counter for the next call.  No float atomics
 // and no inter-work-group waiting, so the result is deterministic and the
 // grid always drains.
+//
+// Cross-XCD visibility without cache maintenance: the partials are written
+// and read with agent-scope atomic stores / loads, which gfx950 performs
+// device-coherently (write-through / miss in the per-XCD L2), and the ticket
+// is only taken once the partial's store has completed.  An agent-scope
+// release/acquire fence would instead write back and invalidate the whole
+// L2 of the XCD in every work-group.
 #pragma once
 
 #include "lift_device.hpp"
@@ -154,6 +161,43 @@ template <> __device__ __forceinline__ float zero_of<float>() { return 0.f; }
 template <> __device__ __forceinline__ double zero_of<double>() { return 0.0; }
 template <> __device__ __forceinline__ Pair zero_of<Pair>() { return Pair{0.f, 0.f}; }
 
+// Agent-coherent (all XCDs) store / load of a partial slot.
+__device__ __forceinline__ void store_coherent(char *p, float v)
+{
+    __hip_atomic_store(reinterpret_cast<uint32_t *>(p), __builtin_bit_cast(uint32_t, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_coherent(char *p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_coherent(char *p, Pair v)
+{
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class S>
+__device__ __forceinline__ S load_coherent(const char *p);
+template <>
+__device__ __forceinline__ float load_coherent<float>(const char *p)
+{
+    return __builtin_bit_cast(float, __hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT));
+}
+template <>
+__device__ __forceinline__ double load_coherent<double>(const char *p)
+{
+    return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT));
+}
+template <>
+__device__ __forceinline__ Pair load_coherent<Pair>(const char *p)
+{
+    return __builtin_bit_cast(Pair, __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT));
+}
+
 template <class S>
 __device__ __forceinline__ void write_result(void *result, int f64, S v)
 {
@@ -221,9 +265,9 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
         V vx[U], vy[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            vx[k] = load_vec<VB>(xv, base + t + k * B);
+            vx[k] = load_stream<VB>(xv, base + t + k * B);
             if constexpr (OP == OP_DOT)
-                vy[k] = load_vec<VB>(yv, base + t + k * B);
+                vy[k] = load_stream<VB>(yv, base + t + k * B);
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -237,9 +281,9 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     // the last, partial step of this work-group
     for (int64_t i = base + t; i < vend; i += B) {
         float fx[E], fy[E];
-        decode<T, VB>(load_vec<VB>(xv, i), fx);
+        decode<T, VB>(load_stream<VB>(xv, i), fx);
         if constexpr (OP == OP_DOT)
-            decode<T, VB>(load_vec<VB>(yv, i), fy);
+            decode<T, VB>(load_stream<VB>(yv, i), fy);
         accumulate<T, OP, ACC, E>(acc, fx, fy);
     }
     // scalar head (work-group 0) and tail (last work-group), fewer than E each
@@ -262,23 +306,22 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     }
 
     unsigned *ticket = reinterpret_cast<unsigned *>(a.ws);
-    ST *slots = reinterpret_cast<ST *>(reinterpret_cast<char *>(a.ws) + WS_HEADER);
+    char *slots = reinterpret_cast<char *>(a.ws) + WS_HEADER;  // 16-byte slots
     if (t == 0) {
-        // slot stride is 16 bytes whatever the slot type
-        *reinterpret_cast<ST *>(reinterpret_cast<char *>(slots) + (int64_t)blockIdx.x * WS_SLOT) =
-            to_slot<ACC>(wg);
-        __threadfence();  // release the partial at agent scope (all XCDs)
-        unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        store_coherent(slots + (int64_t)blockIdx.x * WS_SLOT, to_slot<ACC>(wg));
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         last = (prev == gridDim.x - 1);
     }
     __syncthreads();
     if (!last)
         return;
 
-    __threadfence();  // acquire: every partial is visible from here on
     ST v = zero_of<ST>();
     for (int64_t i = t; i < gridDim.x; i += B)
-        v = merge(v, *reinterpret_cast<const ST *>(reinterpret_cast<const char *>(slots) + i * WS_SLOT));
+        v = merge(v, load_coherent<ST>(slots + i * WS_SLOT));
     v = block_sum<ST>(v, lds_final);
     if (t == 0) {
         write_result(a.result, a.result_f64, v);

@@ -4,7 +4,8 @@
 // o asVector) o split^chunk -- the structure of the paper's vector-scaling
 // example (Fig. 2b) -- with VB-byte vectors, U loads in flight per lane, and
 // a scalar head / tail so any element-aligned pointer pair works.  Every
-// element gets exactly one binary32 multiply.
+// element gets exactly one binary32 multiply.  x is read and out written
+// with nontemporal hints (each byte is touched once).
 #include "lift_device.hpp"
 #include "lift_internal.hpp"
 
@@ -31,7 +32,7 @@ __global__ void __launch_bounds__(1024) scal_kernel_t(ScalArgs a)
     const int t = threadIdx.x;
     const int64_t B = blockDim.x;
     const char *xv = reinterpret_cast<const char *>(a.x) + a.head * 4;
-    V *ov = reinterpret_cast<V *>(reinterpret_cast<char *>(a.out) + a.head * 4);
+    char *ov = reinterpret_cast<char *>(a.out) + a.head * 4;
 
     const int64_t vbeg = (int64_t)blockIdx.x * a.chunk;
     const int64_t vend = min(vbeg + a.chunk, a.nvec);
@@ -41,13 +42,13 @@ __global__ void __launch_bounds__(1024) scal_kernel_t(ScalArgs a)
         V v[U];
 #pragma unroll
         for (int k = 0; k < U; ++k)
-            v[k] = load_vec<VB>(xv, base + t + k * B);
+            v[k] = load_stream<VB>(xv, base + t + k * B);
 #pragma unroll
         for (int k = 0; k < U; ++k)
-            ov[base + t + k * B] = scale_vec<VB>(v[k], a.alpha);
+            store_stream<VB>(ov, base + t + k * B, scale_vec<VB>(v[k], a.alpha));
     }
     for (int64_t i = base + t; i < vend; i += B)
-        ov[i] = scale_vec<VB>(load_vec<VB>(xv, i), a.alpha);
+        store_stream<VB>(ov, i, scale_vec<VB>(load_stream<VB>(xv, i), a.alpha));
 
     if (blockIdx.x == 0 && t < a.head)
         a.out[t] = a.alpha * a.x[t];

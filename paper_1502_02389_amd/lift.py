@@ -219,6 +219,20 @@ def _check_tensor(t, name, dtypes):
         raise ValueError(f"{name} must be contiguous")
 
 
+_STORAGE = None
+
+
+def _tuned(op, dtype, acc, elements):
+    """Knobs from the autotuner's cache for this call shape (None = defaults)."""
+    global _STORAGE
+    torch = _torch()
+    if _STORAGE is None:
+        _STORAGE = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float16: "f16"}
+    from . import tune
+
+    return tune.lookup(op, _STORAGE[dtype], acc, elements)
+
+
 def _ok(status, what):
     if status != LIFT_OK:
         raise LiftError(status, what)
@@ -234,6 +248,8 @@ def scal(alpha, x, out=None, knobs=None):
     if out.numel() != x.numel():
         raise ValueError("out must match x")
     s = _stream_handle(x.device)
+    if knobs is None:
+        knobs = _tuned("scal", x.dtype, "f32", x.numel())
     _ok(lift_scal_ex(x.numel(), float(alpha), x.data_ptr(), out.data_ptr(), knobs, s), "lift_scal")
     return out
 
@@ -252,6 +268,8 @@ def _reduce(which, x, y, acc, result_dtype, knobs):
     s = _stream_handle(x.device)
     accc = ACC[acc] if isinstance(acc, str) else int(acc)
     rt = _dtype_code(result_dtype)
+    if knobs is None and isinstance(acc, str):
+        knobs = _tuned(which, x.dtype, acc, x.numel())
     if which == "asum":
         st = lift_asum_ex(x.numel(), _dtype_code(x.dtype), x.data_ptr(), accc, rt, result.data_ptr(),
                           ws.data_ptr(), ws.numel(), knobs, s)
@@ -293,6 +311,8 @@ def gemv(alpha, A, x, beta, y, acc="f32", knobs=None, lda=None):
         raise ValueError("y must have one entry per row of A")
     s = _stream_handle(A.device)
     accc = ACC[acc] if isinstance(acc, str) else int(acc)
+    if knobs is None and isinstance(acc, str) and m * n > 0:
+        knobs = _tuned("gemv", A.dtype, acc, m * n)
     _ok(lift_gemv_ex(m, n, float(alpha), _dtype_code(A.dtype), A.data_ptr(), lda, x.data_ptr(),
                      float(beta), y.data_ptr(), accc, knobs, s), "lift_gemv")
     return y

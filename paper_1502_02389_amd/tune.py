@@ -1,0 +1,248 @@
+"""Autotuner for the launch knobs.
+
+The paper picks its split factors and vector widths by trying values
+(Section 6.2) and sketches an automatic search (Section 6.3).  This module
+does that search on the device: for one (op, storage, accumulation, size)
+it times every point of a knob grid -- work-group size, bytes per load
+(asVector width), loads in flight per lane, split factor (elements per
+work-group), rows per wavefront for gemv -- and keeps the fastest.
+
+Timing: back-to-back launches bracketed by one HIP event pair on the stream
+the kernels run on, operands rotated over enough copies (>= 1 GiB) that no
+launch finds them in the 256 MB Infinity Cache; best of `trials` repeats.
+
+Results persist in a JSON cache keyed by
+``op/storage/acc/bucket`` (bucket = floor(log2(elements))) plus the device
+name and CU count, so tuning resumes where it stopped and is reused by
+``lift.asum`` & co. when the caller passes no knobs.  ``LIFT_TUNE_CACHE``
+overrides the cache path.
+
+CLI:  python -m paper_1502_02389_amd.tune --ops asum,dot --sizes 24 [--write]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import math
+import os
+import sys
+import threading
+
+from . import lift as B
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+COLD_BYTES = 1 << 30
+
+STORAGE_BYTES = {"f32": 4, "bf16": 2, "f16": 2}
+STORAGE_CODE = {"f32": B.LIFT_F32, "bf16": B.LIFT_BF16, "f16": B.LIFT_F16}
+
+
+def cache_path() -> str:
+    return os.environ.get("LIFT_TUNE_CACHE", DEFAULT_CACHE)
+
+
+def bucket(elements: int) -> int:
+    return int(math.floor(math.log2(elements))) if elements > 0 else 0
+
+
+def key(op: str, storage: str, acc: str, elements: int) -> str:
+    return f"{op}/{storage}/{acc}/{bucket(elements)}"
+
+
+_CACHE = None
+_LOCK = threading.Lock()
+
+
+def load_cache(path: str | None = None) -> dict:
+    global _CACHE
+    path = path or cache_path()
+    with _LOCK:
+        if _CACHE is None or _CACHE.get("_path") != path:
+            try:
+                with open(path) as f:
+                    data = json.load(f)
+            except (OSError, ValueError):
+                data = {"entries": {}}
+            data["_path"] = path
+            _CACHE = data
+    return _CACHE
+
+
+def lookup(op: str, storage: str, acc: str, elements: int):
+    """Tuned knobs for this call shape, or None (library defaults)."""
+    ent = load_cache()["entries"].get(key(op, storage, acc, elements))
+    if not ent:
+        return None
+    return B.knobs(**ent["knobs"])
+
+
+def save_cache(entries: dict, meta: dict, path: str | None = None):
+    path = path or cache_path()
+    data = load_cache(path)
+    data.setdefault("entries", {}).update(entries)
+    data["device"] = meta
+    out = {k: v for k, v in data.items() if k != "_path"}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+# ---------------------------------------------------------------- search space
+
+
+def grid(op: str, storage: str, quick: bool = False):
+    eb = STORAGE_BYTES[storage]
+    if op == "gemv":
+        blocks = (64, 256, 1024) if quick else (64, 128, 256, 512, 1024)
+        vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)
+        for b, v, u, r in itertools.product(blocks, vecs, (1, 2, 4), (1, 2, 4)):
+            yield dict(block=b, vec_bytes=v, unroll=u, rows_per_wave=r)
+        return
+    blocks = (256, 512) if quick else (128, 256, 512, 1024)
+    vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)
+    splits = (0, 1 << 15, 1 << 16, 1 << 17, 1 << 18) if quick else \
+        (0, 1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
+    for b, v, u, s in itertools.product(blocks, vecs, (1, 2, 4, 8), splits):
+        yield dict(block=b, vec_bytes=v, unroll=u, split=s)
+
+
+# ---------------------------------------------------------------- timing
+
+
+class Operands:
+    """Rotating copies of the operands of one call shape, resident on the GPU."""
+
+    def __init__(self, op, storage, elements, m=None, n=None, seed=11):
+        import torch
+
+        self.op, self.storage = op, storage
+        dev = torch.device("cuda:0")
+        g = torch.Generator("cpu").manual_seed(seed)
+        dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[storage]
+        eb = STORAGE_BYTES[storage]
+        if op == "gemv":
+            self.m, self.n = m, n
+            per = m * n * eb
+            self.sets = max(2, -(-COLD_BYTES // per))
+            A = (torch.rand((m, n), generator=g) * 2 - 1).to(dt).to(dev)
+            self.A = [A.clone() for _ in range(self.sets)]
+            self.x = (torch.rand(n, generator=g) * 2 - 1).to(dev)
+            self.y = torch.zeros(m, device=dev)
+            self.bytes = per + 4 * n + 8 * m
+        else:
+            self.n = elements
+            streams = {"scal": 2, "asum": 1, "dot": 2}[op]
+            per = streams * elements * eb
+            self.sets = max(2, -(-COLD_BYTES // per))
+            x = (torch.rand(elements, generator=g) * 2 - 1).to(dt).to(dev)
+            self.x = [x.clone() for _ in range(self.sets)]
+            self.y = [x.clone() for _ in range(self.sets)] if op in ("dot", "scal") else None
+            self.bytes = per
+            self.res = torch.zeros((), dtype=torch.float64, device=dev)
+        self.ws = B.workspace(dev)
+        self.stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def call(self, i, acc, k):
+        s = self.stream
+        if self.op == "scal":
+            st = B.lift_scal_ex(self.n, 1.5, self.x[i].data_ptr(), self.y[i].data_ptr(), k, s)
+        elif self.op == "asum":
+            st = B.lift_asum_ex(self.n, STORAGE_CODE[self.storage], self.x[i].data_ptr(), acc, B.LIFT_F64,
+                                self.res.data_ptr(), self.ws.data_ptr(), self.ws.numel(), k, s)
+        elif self.op == "dot":
+            st = B.lift_dot_ex(self.n, STORAGE_CODE[self.storage], self.x[i].data_ptr(), self.y[i].data_ptr(), acc,
+                               B.LIFT_F64, self.res.data_ptr(), self.ws.data_ptr(), self.ws.numel(), k, s)
+        else:
+            st = B.lift_gemv_ex(self.m, self.n, 1.0, STORAGE_CODE[self.storage], self.A[i].data_ptr(), self.n,
+                                self.x.data_ptr(), 0.5, self.y.data_ptr(), acc, k, s)
+        if st != B.LIFT_OK:
+            raise B.LiftError(st, f"tune {self.op}")
+
+    def time_us(self, acc, k, reps=40, trials=3):
+        import torch
+
+        for i in range(4):
+            self.call(i % self.sets, acc, k)
+        best = float("inf")
+        for _ in range(trials):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(reps):
+                self.call(i % self.sets, acc, k)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e3 / reps)
+        return best
+
+
+def tune_one(op, storage, acc, elements=None, m=None, n=None, quick=False, log=None):
+    """Search the grid for one call shape; returns (best entry, all results)."""
+    ops = Operands(op, storage, elements, m, n)
+    accc = B.ACC[acc]
+    results = []
+    for kn in grid(op, storage, quick):
+        k = B.knobs(**kn)
+        us = ops.time_us(accc, k)
+        gbs = ops.bytes / (us * 1e-6) / 1e9
+        results.append((us, kn, gbs))
+        if log:
+            log(f"{op} {storage} {acc} {kn} {us:.2f} us {gbs:.0f} GB/s")
+    results.sort(key=lambda r: r[0])
+    us, kn, gbs = results[0]
+    return {"knobs": kn, "us": round(us, 3), "GB_s": round(gbs, 1), "bytes": ops.bytes}, results
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="tune lift launch knobs on the current GPU")
+    ap.add_argument("--ops", default="scal,asum,dot,gemv")
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--acc", default="f32")
+    ap.add_argument("--sizes", default="20,24", help="log2 element counts (reductions / scal)")
+    ap.add_argument("--gemv", default="4096x4096,8192x8192", help="MxN shapes for gemv")
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--write", action="store_true", help="merge winners into the cache")
+    ap.add_argument("--top", type=int, default=5)
+    ap.add_argument("--verbose", action="store_true", help="print every knob point")
+    args = ap.parse_args(argv)
+
+    import torch
+
+    props = torch.cuda.get_device_properties(0)
+    meta = {"name": props.name, "cus": props.multi_processor_count, "lib": B.lift_version()}
+    entries = {}
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    for op in args.ops.split(","):
+        for storage in args.storage.split(","):
+            for acc in args.acc.split(","):
+                if op == "scal" and (storage != "f32" or acc != "f32"):
+                    continue
+                shapes = ([tuple(int(v) for v in s.split("x")) for s in args.gemv.split(",")] if op == "gemv"
+                          else [(1 << int(s),) for s in args.sizes.split(",")])
+                for shp in shapes:
+                    if op == "gemv":
+                        best, res = tune_one(op, storage, acc, m=shp[0], n=shp[1], quick=args.quick,
+                                             log=log if args.verbose else None)
+                        elements = shp[0] * shp[1]
+                    else:
+                        best, res = tune_one(op, storage, acc, elements=shp[0], quick=args.quick,
+                                             log=log if args.verbose else None)
+                        elements = shp[0]
+                    k = key(op, storage, acc, elements)
+                    entries[k] = best
+                    log(f"== {k}: best {best}")
+                    for us, kn, gbs in res[: args.top]:
+                        log(f"   {us:8.2f} us {gbs:7.0f} GB/s {kn}")
+                    log(f"   ({len(res)} points; slowest {res[-1][0]:.2f} us)")
+    print(json.dumps({"device": meta, "entries": entries}), flush=True)
+    if args.write:
+        save_cache(entries, meta)
+
+
+if __name__ == "__main__":
+    main()
