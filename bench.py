@@ -12,10 +12,10 @@ finds its operands in the 256 MB Infinity Cache.
 
 Also reported on the same JSON line:
   roofline     : the dominant kernel's algorithmic bytes per launch over its
-                 average duration, from HIP events recorded around it on its
-                 stream inside the timed region; peak 8 TB/s; HBM traffic per
-                 launch from rocprofv3 counters when they were taken on the
-                 current kernel source (else null)
+                 average duration, from HIP events recorded in its own dispatch
+                 packets (lift_time_next_launch) inside the timed region; peak
+                 8 TB/s; HBM traffic per launch from rocprofv3 counters when
+                 they were taken on the current kernel source (else null)
   cpu_baseline : the binary64 oracle (single thread) on a bounded sample of the
                  same workload, same data
   kernels      : per-kernel average durations from back-to-back launches
@@ -134,16 +134,15 @@ def main():
 
     order = ("scal", "asum", "dot")
 
-    def step(i, ev_kernel=None, evs=None):
+    def step(i, ev_kernel=None, ev=None):
         p = ptr[i % nsets]
         for k in order:
             if k == ev_kernel:
-                e0, e1 = evs
-                e0.record(stream)
-                launch(k, p)
-                e1.record(stream)
-            else:
-                launch(k, p)
+                # events recorded inside the kernel's own dispatch packet
+                st = lib.lift_time_next_launch(ev.events[2 * i], ev.events[2 * i + 1])
+                if st != 0:
+                    raise L.LiftError(st, "lift_time_next_launch")
+            launch(k, p)
 
     log("warmup", args.warmup, "sets", nsets)
     for i in range(args.warmup):
@@ -170,18 +169,19 @@ def main():
         log("kernel", k, kernels[k])
     dominant = max(order, key=lambda k: kernels[k]["avg_us"])
 
-    # timed region: K steps, events around the dominant kernel in each step
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+    # timed region: K steps; the dominant kernel of every step is launched
+    # with HIP events embedded in its dispatch (on the stream it runs on)
+    ev = L.HipEvents(2 * args.steps)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        step(i, dominant, evs[i])
+        step(i, dominant, ev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
-    durs = [a.elapsed_time(b) * 1e3 for a, b in evs]
+    durs = [ev.elapsed_ms(2 * i, 2 * i + 1) * 1e3 for i in range(args.steps)]
+    ev.close()
     dom_us = sum(durs) / len(durs)
     achieved = bytes_kernel[dominant] / (dom_us * 1e-6) / 1e9
     log("timed", args.steps, "steps", f"{ms_per_step:.4f} ms/step", f"{value:.1f} GB/s",

@@ -163,6 +163,16 @@ lift_status lift_gemv_ex(int64_t m, int64_t n, float alpha, lift_dtype at, const
 
 /* ---- diagnostics ------------------------------------------------------ */
 
+/* Profiling hook.  The NEXT kernel launched by a lift_* call on the calling
+ * thread is dispatched with `start` and `stop` recorded inside its own
+ * dispatch packet (hipExtLaunchKernel), so hipEventElapsedTime(start, stop)
+ * is that kernel's execution time on its stream, with no extra marker
+ * packets between kernels.  The caller creates both events (hipEventCreate)
+ * on the device of the launch and owns them.  One-shot: the launch clears
+ * it; a call rejected before launching leaves it armed; (NULL, NULL)
+ * disarms it.  Exactly one NULL is LIFT_EINVAL. */
+lift_status lift_time_next_launch(hipEvent_t start, hipEvent_t stop);
+
 /* Static description of a status code. */
 const char *lift_status_string(lift_status status);
 

@@ -8,5 +8,6 @@ from .lift import (  # noqa: F401
     LIFT_EINVAL, LIFT_EUNSUPPORTED, LIFT_EWORKSPACE, LIFT_F16, LIFT_F32, LIFT_F64, LIFT_OK,
     LiftError, asum, dot, gemv, knobs, library, lift_asum, lift_asum_ex, lift_dot, lift_dot_ex,
     lift_gemv, lift_gemv_ex, lift_knobs, lift_last_hip_error, lift_max_workgroups, lift_scal,
-    lift_scal_ex, lift_status_string, lift_version, lift_workspace_bytes, scal, workspace,
+    lift_scal_ex, lift_status_string, lift_time_next_launch, lift_version, lift_workspace_bytes, scal,
+    workspace, HipEvents,
 )

@@ -4,6 +4,7 @@
 // way with or without a GPU.  Launch geometry follows the paper's knobs:
 // the split factor decides how many vectors each work-group owns, the
 // work-group size and vector width pick the kernel instance.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +21,8 @@ using namespace lift;
 namespace {
 
 thread_local int g_last_hip_error = 0;
+thread_local hipEvent_t g_time_start = nullptr;  // armed by lift_time_next_launch
+thread_local hipEvent_t g_time_stop = nullptr;
 
 constexpr int MAX_DEVICES = 64;
 std::atomic<int> g_cu_count[MAX_DEVICES];
@@ -55,7 +58,14 @@ lift_status cu_count(int *out)
 lift_status launch(const void *kernel, int64_t grid, int block, void *args, hipStream_t s)
 {
     void *argv[] = {args};
-    hipError_t e = hipLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)block), argv, 0, s);
+    hipError_t e;
+    if (g_time_start) {
+        e = hipExtLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)block), argv, 0, s, g_time_start,
+                               g_time_stop, 0);
+        g_time_start = g_time_stop = nullptr;
+    } else {
+        e = hipLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)block), argv, 0, s);
+    }
     if (e != hipSuccess)
         return hip_fail(e);
     return LIFT_OK;
@@ -437,6 +447,15 @@ const char *lift_status_string(lift_status s)
 }
 
 int lift_last_hip_error(void) { return g_last_hip_error; }
+
+lift_status lift_time_next_launch(hipEvent_t start, hipEvent_t stop)
+{
+    if ((start == nullptr) != (stop == nullptr))
+        return LIFT_EINVAL;
+    g_time_start = start;
+    g_time_stop = stop;
+    return LIFT_OK;
+}
 
 const char *lift_version(void) { return "lift-mi355x 0.1 gfx950"; }
 

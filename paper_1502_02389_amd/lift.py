@@ -71,6 +71,7 @@ SIGNATURES = {
     "lift_status_string": (ctypes.c_char_p, [_i32]),
     "lift_last_hip_error": (_i32, []),
     "lift_version": (ctypes.c_char_p, []),
+    "lift_time_next_launch": (_i32, [_vp, _vp]),
 }
 
 
@@ -154,6 +155,38 @@ def lift_last_hip_error():
 
 def lift_version():
     return _lib().lift_version().decode()
+
+
+def lift_time_next_launch(start, stop):
+    return _lib().lift_time_next_launch(start, stop)
+
+
+class HipEvents:
+    """Raw HIP events (hipEventCreate) for lift_time_next_launch, via ctypes."""
+
+    def __init__(self, count):
+        self._hip = ctypes.CDLL("libamdhip64.so")
+        self._hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self._hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self._hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.events = []
+        for _ in range(count):
+            ev = ctypes.c_void_p()
+            if self._hip.hipEventCreate(ctypes.byref(ev)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.events.append(ev.value)
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        err = self._hip.hipEventElapsedTime(ctypes.byref(ms), self.events[a], self.events[b])
+        if err != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({err})")
+        return ms.value
+
+    def close(self):
+        for ev in self.events:
+            self._hip.hipEventDestroy(ev)
+        self.events = []
 
 
 # ---------------------------------------------------------------- tensor layer

@@ -157,3 +157,10 @@ def test_tensor_layer_refuses_cpu_tensors():
         L.asum(torch.ones(4))
     with pytest.raises(ValueError, match="GPU"):
         L.scal(2.0, torch.ones(4))
+
+
+@cpu_only
+def test_time_next_launch_argument_rules():
+    assert L.lift_time_next_launch(0x1000, 0) == L.LIFT_EINVAL
+    assert L.lift_time_next_launch(0, 0x1000) == L.LIFT_EINVAL
+    assert L.lift_time_next_launch(0, 0) == L.LIFT_OK

@@ -335,3 +335,22 @@ def test_gemv_beta_zero_ignores_nan_y_and_empty(gpu_device):
     # m = 0: nothing happens
     L.gemv(1.0, torch.zeros((0, 4), device=DEV), torch.zeros(4, device=DEV), 1.0, torch.zeros(0, device=DEV))
     sync()
+
+
+# ------------------------------------------------------------------ profiling hook
+
+
+def test_time_next_launch_brackets_one_kernel(gpu_device):
+    x = W.uniform(1 << 22, W.gen(700)).to(DEV)
+    ev = L.HipEvents(2)
+    banner("timing hook")
+    try:
+        assert L.lift_time_next_launch(ev.events[0], ev.events[1]) == 0
+        r1 = L.asum(x)                      # timed launch
+        r2 = L.asum(x)                      # hook already cleared: plain launch
+        sync()
+        ms = ev.elapsed_ms(0, 1)
+        assert 0.0 < ms < 50.0
+        assert r1.item() == r2.item()
+    finally:
+        ev.close()
