@@ -105,7 +105,13 @@ typedef struct lift_knobs {
     int64_t split;         /* elements per work-group chunk (split^n); the
                               library rounds it up to a whole number of
                               block * unroll loads and caps the grid at
-                              lift_max_workgroups() */
+                              lift_max_workgroups().  Batched form: elements
+                              per tile (gemv tiles: about this many matrix
+                              elements, whole rows) */
+    int32_t wg_per_cu;     /* grid size in work-groups per compute unit when
+                              split is 0 (per-call forms), and the size of
+                              the persistent grid (batched form) */
+    int32_t reserved;      /* must be 0 */
 } lift_knobs;
 
 /* ---- plain FP32 forms (Fig. 5) --------------------------------------- */
@@ -160,6 +166,67 @@ lift_status lift_dot_ex(int64_t n, lift_dtype xt, const void *x, const void *y, 
 lift_status lift_gemv_ex(int64_t m, int64_t n, float alpha, lift_dtype at, const void *A,
                          int64_t lda, const float *x, float beta, float *y, lift_acc acc,
                          const lift_knobs *knobs, hipStream_t stream);
+
+/* ---- batched form ------------------------------------------------------ */
+
+/* Many asum / dot / gemv problems of uneven size in ONE kernel launch.
+ * The paper's split and map-workgroup applied to a list of problems: every
+ * problem is cut into tiles (split^n), and a persistent grid of work-groups
+ * takes tiles from a shared counter until none are left.  The partials of a
+ * reduction are combined by whichever work-group finishes its last tile, in
+ * tile order, so results do not depend on which work-group ran which tile. */
+typedef enum lift_kind {
+    LIFT_KIND_ASUM = 0,
+    LIFT_KIND_DOT = 1,
+    LIFT_KIND_GEMV = 2
+} lift_kind;
+
+/* One problem; all pointers are device pointers, owned by the caller. */
+typedef struct lift_problem {
+    int32_t kind;      /* lift_kind */
+    int32_t reserved;  /* must be 0 */
+    int64_t m;         /* gemv: rows of A (ignored otherwise) */
+    int64_t n;         /* asum / dot: elements; gemv: columns of A */
+    int64_t lda;       /* gemv: leading dimension, >= max(1, n) */
+    const void *a;     /* asum / dot: x (batch storage type); gemv: A (batch storage type) */
+    const void *b;     /* dot: y (batch storage type); gemv: x (binary32); asum: unused */
+    void *out;         /* asum / dot: result (batch result type); gemv: y (binary32, in/out) */
+    float alpha;       /* gemv only */
+    float beta;        /* gemv only; 0 means y is not read */
+} lift_problem;
+
+typedef struct lift_batch lift_batch;
+
+/* Plan a batch on the current device: checks every problem as the per-call
+ * entry points do, builds the tile table (tiles sorted largest first), and
+ * allocates and fills one device buffer for descriptors, tiles, partial
+ * slots and counters (this call allocates and synchronises; lift_batch_run
+ * does neither).  storage: F32, BF16 or F16 for every x, y and A; rt: F32 or
+ * F64 for reduction results.  The pointers inside `probs` are recorded: the
+ * batch computes on whatever those buffers hold at run time.  On error
+ * *out is NULL; LIFT_EINVAL names a bad problem or argument. */
+lift_status lift_batch_create(const lift_problem *probs, int32_t count, lift_dtype storage,
+                              lift_acc acc, lift_dtype rt, const lift_knobs *knobs,
+                              lift_batch **out);
+
+/* Enqueue the whole batch as one kernel on `stream`.  Allocation-free and
+ * memset-free: the kernel leaves its counters reset, so the call can be
+ * captured into a HIP graph and replayed.  Runs of one batch must not
+ * overlap (they share the counters). */
+lift_status lift_batch_run(lift_batch *batch, hipStream_t stream);
+
+/* Capture lift_batch_run on `stream` (which must not be the null stream)
+ * into a HIP graph and instantiate it; the caller replays *exec with
+ * hipGraphLaunch and destroys it with hipGraphExecDestroy. */
+lift_status lift_batch_capture(lift_batch *batch, hipStream_t stream, hipGraphExec_t *exec);
+
+/* Tiles in the plan, work-groups in the persistent grid, and algorithmic
+ * HBM bytes of one run (each x, y, A element read once, y of gemv read
+ * (beta != 0) and written, results written).  Any pointer may be NULL. */
+lift_status lift_batch_info(const lift_batch *batch, int64_t *tiles, int64_t *grid, int64_t *bytes);
+
+/* Free the batch's device memory (synchronises its device).  NULL is a no-op. */
+void lift_batch_destroy(lift_batch *batch);
 
 /* ---- diagnostics ------------------------------------------------------ */
 

@@ -9,5 +9,6 @@ from .lift import (  # noqa: F401
     LiftError, asum, dot, gemv, knobs, library, lift_asum, lift_asum_ex, lift_dot, lift_dot_ex,
     lift_gemv, lift_gemv_ex, lift_knobs, lift_last_hip_error, lift_max_workgroups, lift_scal,
     lift_scal_ex, lift_status_string, lift_time_next_launch, lift_version, lift_workspace_bytes, scal,
-    workspace, HipEvents,
+    workspace, HipEvents, Batch, GraphRun, lift_problem, lift_batch_create, lift_batch_run,
+    lift_batch_capture, lift_batch_info, lift_batch_destroy, LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV,
 )

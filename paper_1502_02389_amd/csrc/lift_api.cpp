@@ -12,6 +12,10 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <new>
+#include <numeric>
+#include <utility>
+#include <vector>
 
 #include "lift.h"
 #include "lift_internal.hpp"
@@ -102,6 +106,7 @@ bool pow2_in(int64_t v, int64_t lo, int64_t hi)
 struct Knobs {
     int block, vec_bytes, unroll, rows;
     int64_t split;
+    int wg_per_cu;
 };
 
 // Checks the caller's knobs (0 = default) and merges them with defaults.
@@ -134,17 +139,20 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
         return LIFT_EINVAL;
     if (k->split)
         out->split = k->split;
+    if (k->wg_per_cu < 0 || k->wg_per_cu > 64 || k->reserved != 0)
+        return LIFT_EINVAL;
+    if (k->wg_per_cu)
+        out->wg_per_cu = k->wg_per_cu;
     return LIFT_OK;
 }
 
 // Defaults, from the knob search on MI355X (256 CUs): reductions run about
 // one long-lived work-group per CU (fewer partials, shorter combine tail),
 // scal many one-step work-groups, gemv small work-groups of row wavefronts.
-constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0};
-constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0};
-constexpr Knobs DEF_GEMV = {128, 16, 4, 1, 0};
-constexpr int64_t WG_PER_CU_SCAL = 32;    // default grid for scal
-constexpr int64_t WG_PER_CU_REDUCE = 1;   // default grid for asum / dot
+constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0, 32};
+constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1};
+constexpr Knobs DEF_GEMV = {128, 16, 4, 1, 0, 0};
+constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2};
 
 // Split a range of n elements of `ebytes` bytes at base address p into a
 // scalar head (up to the first vb-aligned address), whole vb-byte vectors,
@@ -171,9 +179,9 @@ bool split3(const void *p, const void *q, int64_t n, int ebytes, int vb, Split3 
 
 // Vectors per work-group: the requested split (elements) or the default
 // grid, rounded up to whole block * unroll steps, with the grid capped.
-int64_t chunk_for(int64_t nvec, int64_t elems_per_vec, const Knobs &k, int cus, int64_t wg_per_cu,
-                  int64_t max_wg)
+int64_t chunk_for(int64_t nvec, int64_t elems_per_vec, const Knobs &k, int cus, int64_t max_wg)
 {
+    const int64_t wg_per_cu = k.wg_per_cu;
     const int64_t step = (int64_t)k.block * k.unroll;
     int64_t chunk;
     if (k.split > 0) {
@@ -261,7 +269,7 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
     if (st != LIFT_OK)
         return st;
     const int64_t e = vb / eb;
-    const int64_t chunk = chunk_for(sp.nvec, e, k, cus, WG_PER_CU_REDUCE, MAX_WORKGROUPS);
+    const int64_t chunk = chunk_for(sp.nvec, e, k, cus, MAX_WORKGROUPS);
     const int64_t grid = std::max<int64_t>(1, (sp.nvec + chunk - 1) / chunk);
 
     ReduceArgs a;
@@ -337,6 +345,235 @@ lift_status gemv_common(int64_t m, int64_t n, float alpha, int at, const void *A
     return launch(kern, grid, k.block, &a, stream);
 }
 
+const void *batch_table(int dt, int acc, int vb, int unroll)
+{
+    switch (dt) {
+    case LIFT_F32: return batch_kernel_f32(acc, vb, unroll);
+    case LIFT_BF16: return batch_kernel_bf16(acc, vb, unroll);
+    case LIFT_F16: return batch_kernel_f16(acc, vb, unroll);
+    default: return nullptr;
+    }
+}
+
+// True if any interval of `outs` shares a byte with another interval of
+// `outs` or with any interval of `ins` ([begin, end) byte ranges).
+bool any_overlap(std::vector<std::pair<uintptr_t, uintptr_t>> outs,
+                 std::vector<std::pair<uintptr_t, uintptr_t>> ins)
+{
+    std::sort(outs.begin(), outs.end());
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i].first < outs[i - 1].second)
+            return true;
+    std::sort(ins.begin(), ins.end());
+    // prefix maximum of input ends, to test each output against every input
+    std::vector<uintptr_t> maxend(ins.size());
+    uintptr_t m = 0;
+    for (size_t i = 0; i < ins.size(); ++i)
+        maxend[i] = m = std::max(m, ins[i].second);
+    for (const auto &o : outs) {
+        // inputs starting before o.second; overlap if any of them ends after o.first
+        size_t k = std::lower_bound(ins.begin(), ins.end(), std::make_pair(o.second, (uintptr_t)0)) - ins.begin();
+        if (k > 0 && maxend[k - 1] > o.first)
+            return true;
+    }
+    return false;
+}
+
+}  // namespace
+
+struct lift_batch {
+    int device = 0;
+    int64_t ntiles = 0;
+    int64_t nprobs = 0;
+    int64_t grid = 0;
+    int64_t bytes = 0;
+    int block = 0;
+    void *dmem = nullptr;
+    const void *kern = nullptr;
+    BatchArgs args{};
+};
+
+namespace {
+
+lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, int acc, int rt,
+                       const lift_knobs *knobs, lift_batch *b)
+{
+    if (count < 0 || (count > 0 && !probs))
+        return LIFT_EINVAL;
+    if (storage != LIFT_F32 && storage != LIFT_BF16 && storage != LIFT_F16)
+        return LIFT_EINVAL;
+    if (acc != LIFT_ACC_F32 && acc != LIFT_ACC_F32_COMP && acc != LIFT_ACC_F32_F64COMBINE)
+        return LIFT_EINVAL;
+    if (rt != LIFT_F32 && rt != LIFT_F64)
+        return LIFT_EINVAL;
+    const int eb = elem_bytes(storage), rb = elem_bytes(rt);
+    Knobs k;
+    lift_status st = resolve(knobs, DEF_BATCH, eb, &k);
+    if (st != LIFT_OK)
+        return st;
+    if (k.vec_bytes < 4)
+        return LIFT_EUNSUPPORTED;  // the batched kernels load at least a dword per lane
+    const int vb = k.vec_bytes;
+    const int64_t e = vb / eb;
+
+    std::vector<std::pair<uintptr_t, uintptr_t>> outs, ins;
+    std::vector<BatchProblem> hp((size_t)count);
+    std::vector<BatchTile> tiles;
+    std::vector<int64_t> cost;
+    int64_t slots = 0, bytes = 0;
+    const int64_t step = (int64_t)k.block * k.unroll;
+    const int64_t waves = k.block / 64;
+    for (int32_t i = 0; i < count; ++i) {
+        const lift_problem &q = probs[i];
+        BatchProblem &p = hp[(size_t)i];
+        std::memset(&p, 0, sizeof p);
+        if (q.reserved != 0)
+            return LIFT_EINVAL;
+        p.kind = q.kind;
+        p.n = q.n;
+        p.a = q.a;
+        p.b = q.b;
+        p.out = q.out;
+        p.alpha = q.alpha;
+        p.beta = q.beta;
+        if (q.kind == LIFT_KIND_ASUM || q.kind == LIFT_KIND_DOT) {
+            const bool dot = q.kind == LIFT_KIND_DOT;
+            if (q.n < 0 || !q.out || !aligned(q.out, rb))
+                return LIFT_EINVAL;
+            if (q.n > 0 && (!q.a || !aligned(q.a, eb) || (dot && (!q.b || !aligned(q.b, eb)))))
+                return LIFT_EINVAL;
+            outs.push_back({(uintptr_t)q.out, (uintptr_t)q.out + rb});
+            if (q.n > 0) {
+                ins.push_back({(uintptr_t)q.a, (uintptr_t)q.a + q.n * eb});
+                if (dot)
+                    ins.push_back({(uintptr_t)q.b, (uintptr_t)q.b + q.n * eb});
+            }
+            Split3 sp{0, 0};
+            int64_t unit_e = e;
+            p.vec = 1;
+            if (q.n > 0 && !split3(q.a, dot ? q.b : nullptr, q.n, eb, vb, &sp)) {
+                p.vec = 0;
+                unit_e = 1;
+                sp.head = 0;
+                sp.nvec = q.n;
+            }
+            p.head = sp.head;
+            p.nvec = sp.nvec;
+            // tile length in units (vectors or elements), whole steps
+            int64_t len = std::max<int64_t>(1, (k.split + unit_e - 1) / unit_e);
+            len = (len + step - 1) / step * step;
+            const int64_t nt = std::max<int64_t>(1, (p.nvec + len - 1) / len);
+            if (nt > INT32_MAX)
+                return LIFT_EUNSUPPORTED;
+            p.ntiles = (int32_t)nt;
+            p.slot_base = slots;
+            slots += nt;
+            for (int64_t t = 0; t < nt; ++t) {
+                BatchTile tl{i, (int32_t)t, t * len, std::min(len, p.nvec - t * len)};
+                if (tl.len < 0)
+                    tl.len = 0;
+                tiles.push_back(tl);
+                cost.push_back(tl.len * unit_e * eb * (dot ? 2 : 1));
+            }
+            bytes += q.n * eb * (dot ? 2 : 1) + rb;
+        } else if (q.kind == LIFT_KIND_GEMV) {
+            if (q.m < 0 || q.n < 0 || q.lda < std::max<int64_t>(1, q.n))
+                return LIFT_EINVAL;
+            p.m = q.m;
+            p.lda = q.lda;
+            if (q.m > 0 && (!q.out || !aligned(q.out, 4)))
+                return LIFT_EINVAL;
+            if (q.m > 0 && q.n > 0 && (!q.a || !q.b || !aligned(q.a, eb) || !aligned(q.b, 4)))
+                return LIFT_EINVAL;
+            if (q.m == 0)
+                continue;
+            outs.push_back({(uintptr_t)q.out, (uintptr_t)q.out + q.m * 4});
+            if (q.n > 0) {
+                ins.push_back({(uintptr_t)q.a, (uintptr_t)q.a + ((q.m - 1) * q.lda + q.n) * eb});
+                ins.push_back({(uintptr_t)q.b, (uintptr_t)q.b + q.n * 4});
+            }
+            const int64_t xalign = std::min<int64_t>(e * 4, 16);
+            p.vec = q.n > 0 && aligned(q.a, vb) && (q.lda * eb) % vb == 0 && aligned(q.b, xalign);
+            p.nvec = p.vec ? q.n / e : q.n;
+            int64_t rows = std::max<int64_t>(1, k.split / std::max<int64_t>(1, q.n));
+            rows = (rows + waves - 1) / waves * waves;
+            const int64_t nt = (q.m + rows - 1) / rows;
+            if (nt > INT32_MAX)
+                return LIFT_EUNSUPPORTED;
+            p.ntiles = (int32_t)nt;
+            for (int64_t t = 0; t < nt; ++t) {
+                BatchTile tl{i, (int32_t)t, t * rows, std::min(rows, q.m - t * rows)};
+                tiles.push_back(tl);
+                cost.push_back(tl.len * std::max<int64_t>(q.n, 1) * eb);
+            }
+            bytes += q.m * q.n * eb + q.n * 4 + q.m * 4 + (q.beta != 0.f ? q.m * 4 : 0);
+        } else {
+            return LIFT_EINVAL;
+        }
+    }
+    if (any_overlap(outs, ins))
+        return LIFT_EINVAL;
+    if ((int64_t)tiles.size() > INT32_MAX || count > 0x7fffffff)
+        return LIFT_EUNSUPPORTED;
+
+    // largest tiles first, so the dynamic schedule ends on small ones
+    std::vector<int64_t> order(tiles.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+    std::vector<BatchTile> sorted(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        sorted[i] = tiles[(size_t)order[i]];
+
+    const void *kern = batch_table(storage, acc, vb, k.unroll);
+    if (!kern)
+        return LIFT_EUNSUPPORTED;
+    int cus = 0;
+    st = cu_count(&cus);
+    if (st != LIFT_OK)
+        return st;
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess)
+        return hip_fail(he);
+
+    // one allocation: counters | per-problem counters | problems | tiles | slots
+    auto up = [](int64_t v) { return (v + 255) / 256 * 256; };
+    const int64_t off_pc = 256;
+    const int64_t off_pr = off_pc + up(std::max<int64_t>(count, 1) * 4);
+    const int64_t off_ti = off_pr + up(std::max<int64_t>(count, 1) * (int64_t)sizeof(BatchProblem));
+    const int64_t off_sl = off_ti + up(std::max<int64_t>((int64_t)sorted.size(), 1) * (int64_t)sizeof(BatchTile));
+    const int64_t total = off_sl + std::max<int64_t>(slots, 1) * WS_SLOT;
+    void *mem = nullptr;
+    he = hipMalloc(&mem, (size_t)total);
+    if (he != hipSuccess)
+        return hip_fail(he);
+    char *base = (char *)mem;
+    if ((he = hipMemset(base, 0, (size_t)off_pr)) != hipSuccess ||
+        (count > 0 && (he = hipMemcpy(base + off_pr, hp.data(), hp.size() * sizeof(BatchProblem),
+                                      hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!sorted.empty() && (he = hipMemcpy(base + off_ti, sorted.data(), sorted.size() * sizeof(BatchTile),
+                                            hipMemcpyHostToDevice)) != hipSuccess)) {
+        hipFree(mem);
+        return hip_fail(he);
+    }
+    b->device = dev;
+    b->ntiles = (int64_t)sorted.size();
+    b->nprobs = count;
+    b->bytes = bytes;
+    b->block = k.block;
+    b->grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * k.wg_per_cu, b->ntiles));
+    b->dmem = mem;
+    b->kern = kern;
+    b->args.probs = (const BatchProblem *)(base + off_pr);
+    b->args.tiles = (const BatchTile *)(base + off_ti);
+    b->args.counters = (unsigned *)base;
+    b->args.pcount = (unsigned *)(base + off_pc);
+    b->args.slots = base + off_sl;
+    b->args.ntiles = b->ntiles;
+    b->args.result_f64 = rt == LIFT_F64;
+    return LIFT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -375,7 +612,7 @@ lift_status lift_scal_ex(int64_t n, float alpha, const float *x, float *out, con
     st = cu_count(&cus);
     if (st != LIFT_OK)
         return st;
-    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, WG_PER_CU_SCAL, INT32_MAX);
+    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, INT32_MAX);
     const int64_t grid = std::max<int64_t>(1, (sp.nvec + chunk - 1) / chunk);
     ScalArgs a;
     a.x = x;
@@ -432,6 +669,89 @@ lift_status lift_gemv_ex(int64_t m, int64_t n, float alpha, lift_dtype at, const
                          const lift_knobs *knobs, hipStream_t stream)
 {
     return gemv_common(m, n, alpha, at, A, lda, x, beta, y, acc, knobs, stream);
+}
+
+lift_status lift_batch_create(const lift_problem *probs, int32_t count, lift_dtype storage, lift_acc acc,
+                              lift_dtype rt, const lift_knobs *knobs, lift_batch **out)
+{
+    if (!out)
+        return LIFT_EINVAL;
+    *out = nullptr;
+    lift_batch *b = new (std::nothrow) lift_batch();
+    if (!b)
+        return LIFT_EUNSUPPORTED;
+    lift_status st = batch_plan(probs, count, storage, acc, rt, knobs, b);
+    if (st != LIFT_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return LIFT_OK;
+}
+
+lift_status lift_batch_run(lift_batch *b, hipStream_t stream)
+{
+    if (!b)
+        return LIFT_EINVAL;
+    if (b->ntiles == 0)
+        return LIFT_OK;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    if (dev != b->device)
+        return LIFT_EINVAL;
+    BatchArgs a = b->args;
+    return launch(b->kern, b->grid, b->block, &a, stream);
+}
+
+lift_status lift_batch_capture(lift_batch *b, hipStream_t stream, hipGraphExec_t *exec)
+{
+    if (!b || !exec || !stream)
+        return LIFT_EINVAL;
+    *exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    lift_status st = lift_batch_run(b, stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(stream, &graph);
+    if (st != LIFT_OK) {
+        if (graph)
+            hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess)
+        return hip_fail(e);
+    e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        *exec = nullptr;
+        return hip_fail(e);
+    }
+    return LIFT_OK;
+}
+
+lift_status lift_batch_info(const lift_batch *b, int64_t *tiles, int64_t *grid, int64_t *bytes)
+{
+    if (!b)
+        return LIFT_EINVAL;
+    if (tiles)
+        *tiles = b->ntiles;
+    if (grid)
+        *grid = b->grid;
+    if (bytes)
+        *bytes = b->bytes;
+    return LIFT_OK;
+}
+
+void lift_batch_destroy(lift_batch *b)
+{
+    if (!b)
+        return;
+    if (b->dmem)
+        hipFree(b->dmem);
+    delete b;
 }
 
 const char *lift_status_string(lift_status s)

@@ -1,0 +1,206 @@
+// Batched form: every asum / dot / gemv of a problem list in one launch.
+//
+// The paper's split and map-workgroup over a list of problems.  The host cuts
+// every problem into tiles (reductions: runs of vectors; gemv: runs of rows)
+// and sorts them largest first.  A persistent grid of work-groups takes the
+// next tile from an agent-scope counter until the table is exhausted:
+//   reduction tile -> the per-call streaming body (lane reduce-seq, DPP wave
+//                     butterfly, LDS across waves) -> partial slot of the tile;
+//                     the work-group that finishes a problem's last tile folds
+//                     that problem's partials in tile order and writes its
+//                     result;
+//   gemv tile      -> each wavefront takes rows of the tile (gemv_row_group).
+// Tile-to-work-group assignment is dynamic, but every tile's arithmetic and
+// every combine order are fixed by the plan, so results are deterministic.
+// The last work-group to leave resets the tile counter, so the launch can be
+// replayed from a HIP graph without a memset node.
+#pragma once
+
+#include "lift_gemv.hpp"
+#include "lift_reduce.hpp"
+
+namespace lift {
+
+// Streaming phase of one reduction tile: the calling lane's partial.
+template <class T, int OP, int ACC, int VB, int U>
+__device__ __forceinline__ typename BlockT<ACC>::type tile_lane_value(const BatchProblem &p, const BatchTile &tl)
+{
+    constexpr int E = Elems<T, VB>::value;
+    using V = typename Vec<VB>::type;
+    const int t = threadIdx.x;
+    const int64_t B = blockDim.x;
+    const char *xv = reinterpret_cast<const char *>(p.a) + p.head * T::bytes;
+    const char *yv = OP == OP_DOT ? reinterpret_cast<const char *>(p.b) + p.head * T::bytes : nullptr;
+    const int64_t vbeg = tl.begin, vend = tl.begin + tl.len, step = B * U;
+
+    LaneAcc<ACC, E> acc;
+    int64_t base = vbeg;
+    for (; base + step <= vend; base += step) {
+        V vx[U], vy[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            vx[k] = load_stream<VB>(xv, base + t + k * B);
+            if constexpr (OP == OP_DOT)
+                vy[k] = load_stream<VB>(yv, base + t + k * B);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            float fx[E], fy[E];
+            decode<T, VB>(vx[k], fx);
+            if constexpr (OP == OP_DOT)
+                decode<T, VB>(vy[k], fy);
+            accumulate<T, OP, ACC, E>(acc, fx, fy);
+        }
+    }
+    for (int64_t i = base + t; i < vend; i += B) {
+        float fx[E], fy[E];
+        decode<T, VB>(load_stream<VB>(xv, i), fx);
+        if constexpr (OP == OP_DOT)
+            decode<T, VB>(load_stream<VB>(yv, i), fy);
+        accumulate<T, OP, ACC, E>(acc, fx, fy);
+    }
+    if (tl.index == 0 && t < p.head) {
+        float fy = OP == OP_DOT ? load_elem<T>(p.b, t) : 0.f;
+        accumulate_scalar<T, OP, ACC, E>(acc, load_elem<T>(p.a, t), fy);
+    }
+    const int64_t tail0 = p.head + p.nvec * E;
+    if (tl.index == p.ntiles - 1 && t < p.n - tail0) {
+        float fy = OP == OP_DOT ? load_elem<T>(p.b, tail0 + t) : 0.f;
+        accumulate_scalar<T, OP, ACC, E>(acc, load_elem<T>(p.a, tail0 + t), fy);
+    }
+    return acc.value();
+}
+
+// Rows [begin, begin + len) of a gemv problem: wavefront w takes rows
+// begin + w, begin + w + W, ... (W wavefronts per work-group).
+template <class T, int ACC, int VB, int U>
+__device__ __forceinline__ void gemv_tile(const BatchProblem &p, const BatchTile &tl)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = blockDim.x >> 6;
+    const float *x = reinterpret_cast<const float *>(p.b);
+    float *y = reinterpret_cast<float *>(p.out);
+    for (int64_t r = tl.begin + (threadIdx.x >> 6); r < tl.begin + tl.len; r += waves)
+        gemv_row_group<T, ACC, VB, 1, U>(p.a, x, y, p.m, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
+}
+
+// Next tile for the work-group: thread 0 draws it from the shared counter,
+// everyone reads it after a barrier.  Wave-uniform (scalar) result.
+__device__ __forceinline__ int fetch_tile(unsigned *counter, int *s_tile)
+{
+    if (threadIdx.x == 0)
+        *s_tile = (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int ti = __builtin_amdgcn_readfirstlane(*s_tile);
+    __syncthreads();  // every wave has read s_tile before thread 0 may write it again
+    return ti;
+}
+
+// The loop is written so that its only back edge passes through fetch_tile:
+// no continue / break, and every branch inside it is on a work-group-uniform
+// scalar.  (A loop whose head is thread 0's conditional fetch, re-entered
+// from several places, can be restructured by the compiler into a back edge
+// that reaches the barrier without the fetch, splitting wave 0 around it.)
+template <class T, int ACC, int VB, int U>
+__global__ void __launch_bounds__(1024) batch_kernel(BatchArgs a)
+{
+    using BT = typename BlockT<ACC>::type;
+    using ST = typename SlotT<ACC>::type;
+    constexpr int EB = T::bytes;  // element-wise loads for unaligned problems
+    __shared__ BT lds_block[16];
+    __shared__ ST lds_final[16];
+    __shared__ int s_tile;
+    __shared__ int s_last;
+    const int t = threadIdx.x;
+    const int64_t B = blockDim.x;
+
+    int ti = fetch_tile(&a.counters[0], &s_tile);
+    while (ti < a.ntiles) {
+        const BatchTile tl = a.tiles[ti];
+        const BatchProblem p = a.probs[tl.problem];
+        const int kind = __builtin_amdgcn_readfirstlane(p.kind);
+        const int vec = __builtin_amdgcn_readfirstlane(p.vec);
+
+        if (kind == KIND_GEMV) {
+            if (vec)
+                gemv_tile<T, ACC, VB, U>(p, tl);
+            else
+                gemv_tile<T, ACC, EB, U>(p, tl);
+        } else {
+            BT v;
+            if (kind == KIND_ASUM)
+                v = vec ? tile_lane_value<T, OP_ASUM, ACC, VB, U>(p, tl) : tile_lane_value<T, OP_ASUM, ACC, EB, U>(p, tl);
+            else
+                v = vec ? tile_lane_value<T, OP_DOT, ACC, VB, U>(p, tl) : tile_lane_value<T, OP_DOT, ACC, EB, U>(p, tl);
+            const BT wg = block_sum<BT>(v, lds_block);
+
+            if (t == 0) {
+                store_coherent(a.slots + (p.slot_base + tl.index) * WS_SLOT, to_slot<ACC>(wg));
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                unsigned prev = __hip_atomic_fetch_add(&a.pcount[tl.problem], 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                s_last = prev == (unsigned)(p.ntiles - 1);
+            }
+            __syncthreads();
+            const int last = __builtin_amdgcn_readfirstlane(s_last);
+            if (last) {
+                ST acc = zero_of<ST>();
+                for (int64_t i = t; i < p.ntiles; i += B)
+                    acc = merge(acc, load_coherent<ST>(a.slots + (p.slot_base + i) * WS_SLOT));
+                acc = block_sum<ST>(acc, lds_final);
+                if (t == 0) {
+                    write_result(p.out, a.result_f64, acc);
+                    __hip_atomic_store(&a.pcount[tl.problem], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        ti = fetch_tile(&a.counters[0], &s_tile);
+    }
+
+    // The last work-group out resets the counters for the next launch.
+    if (t == 0) {
+        unsigned prev = __hip_atomic_fetch_add(&a.counters[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(&a.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <class T, int ACC, int VB>
+const void *batch_pick_unroll(int unroll)
+{
+    switch (unroll) {
+    case 1: return reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 1>);
+    case 2: return reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 2>);
+    case 4: return reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 4>);
+    case 8: return reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 8>);
+    default: return nullptr;
+    }
+}
+
+template <class T, int ACC>
+const void *batch_pick_vec(int vec_bytes, int unroll)
+{
+    switch (vec_bytes) {
+    case 4: return batch_pick_unroll<T, ACC, 4>(unroll);
+    case 8: return batch_pick_unroll<T, ACC, 8>(unroll);
+    case 16: return batch_pick_unroll<T, ACC, 16>(unroll);
+    default: return nullptr;
+    }
+}
+
+template <class T>
+const void *pick_batch(int acc, int vec_bytes, int unroll)
+{
+    switch (acc) {
+    case ACC_F32: return batch_pick_vec<T, ACC_F32>(vec_bytes, unroll);
+    case ACC_COMP: return batch_pick_vec<T, ACC_COMP>(vec_bytes, unroll);
+    case ACC_F64: return batch_pick_vec<T, ACC_F64>(vec_bytes, unroll);
+    default: return nullptr;
+    }
+}
+
+}  // namespace lift

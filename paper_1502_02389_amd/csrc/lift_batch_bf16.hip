@@ -1,0 +1,11 @@
+// Batched-form kernels for BF16 storage (instantiations of lift_batch.hpp).
+#include "lift_batch.hpp"
+
+namespace lift {
+
+const void *batch_kernel_bf16(int acc, int vec_bytes, int unroll)
+{
+    return pick_batch<BF16>(acc, vec_bytes, unroll);
+}
+
+}  // namespace lift

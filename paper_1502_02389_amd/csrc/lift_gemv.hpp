@@ -113,82 +113,90 @@ __device__ __forceinline__ void store_row(float *y, int64_t i, float alpha, floa
     y[i] = fmaf(alpha, dotv, by);
 }
 
+// Rows r0 .. r0 + R - 1 (clamped to m) of y = alpha * A x + beta * y, by one
+// wavefront; `lane` is the lane index.  nvec = whole VB-byte vectors per row.
 template <class T, int ACC, int VB, int R, int U>
-__global__ void __launch_bounds__(1024) gemv_kernel(GemvArgs a)
+__device__ __forceinline__ void gemv_row_group(const void *A, const float *x, float *y, int64_t m, int64_t n,
+                                               int64_t lda, int64_t nvec, float alpha, float beta, int64_t r0,
+                                               int lane)
 {
     constexpr int E = Elems<T, VB>::value;
     using V = typename Vec<VB>::type;
+    const int64_t row_bytes = lda * T::bytes;
+    const int64_t tail0 = nvec * E;
+    const char *rows[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        rows[r] = reinterpret_cast<const char *>(A) + min(r0 + r, m - 1) * row_bytes;
+
+    RowAcc<ACC, E> acc[R];
+    int64_t base = 0;
+    for (; base + 64 * U <= nvec; base += 64 * U) {
+        float xf[U][E];
+        V va[R][U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            load_x<E>(x, base + lane + 64 * k, xf[k]);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                va[r][k] = load_stream<VB>(rows[r], base + lane + 64 * k);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                float af[E];
+                decode<T, VB>(va[r][k], af);
+                acc[r].add(af, xf[k]);
+            }
+    }
+    for (int64_t v = base + lane; v < nvec; v += 64) {
+        float xf[E];
+        load_x<E>(x, v, xf);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float af[E];
+            decode<T, VB>(load_stream<VB>(rows[r], v), af);
+            acc[r].add(af, xf);
+        }
+    }
+    if (tail0 + lane < n) {  // fewer than E trailing columns
+        float xs = x[tail0 + lane];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            acc[r].add_scalar(load_elem<T>(rows[r], tail0 + lane), xs);
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if constexpr (ACC == ACC_F64) {
+            double d = wave_sum((double)acc[r].value());
+            if (lane == 0 && r0 + r < m) {
+                double by = beta == 0.f ? 0.0 : (double)beta * (double)y[r0 + r];
+                y[r0 + r] = (float)((double)alpha * d + by);
+            }
+        } else if constexpr (ACC == ACC_COMP) {
+            Pair p = wave_sum(acc[r].value());
+            if (lane == 0 && r0 + r < m)
+                store_row<ACC>(y, r0 + r, alpha, beta, p.s + p.c);
+        } else {
+            float d = wave_sum(acc[r].value());
+            if (lane == 0 && r0 + r < m)
+                store_row<ACC>(y, r0 + r, alpha, beta, d);
+        }
+    }
+}
+
+template <class T, int ACC, int VB, int R, int U>
+__global__ void __launch_bounds__(1024) gemv_kernel(GemvArgs a)
+{
     const int lane = threadIdx.x & 63;
     const int64_t wpb = blockDim.x >> 6;
     const int64_t gw = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * wpb;
-    const int64_t row_bytes = a.lda * T::bytes;
-    const int64_t tail0 = a.nvec * E;
-
-    for (int64_t r0 = gw * R; r0 < a.m; r0 += nw * R) {  // wave-uniform loop
-        const char *rows[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            rows[r] = reinterpret_cast<const char *>(a.A) + min(r0 + r, a.m - 1) * row_bytes;
-
-        RowAcc<ACC, E> acc[R];
-        int64_t base = 0;
-        for (; base + 64 * U <= a.nvec; base += 64 * U) {
-            float xf[U][E];
-            V va[R][U];
-#pragma unroll
-            for (int k = 0; k < U; ++k)
-                load_x<E>(a.x, base + lane + 64 * k, xf[k]);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int k = 0; k < U; ++k)
-                    va[r][k] = load_stream<VB>(rows[r], base + lane + 64 * k);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    float af[E];
-                    decode<T, VB>(va[r][k], af);
-                    acc[r].add(af, xf[k]);
-                }
-        }
-        for (int64_t v = base + lane; v < a.nvec; v += 64) {
-            float xf[E];
-            load_x<E>(a.x, v, xf);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                float af[E];
-                decode<T, VB>(load_stream<VB>(rows[r], v), af);
-                acc[r].add(af, xf);
-            }
-        }
-        if (tail0 + lane < a.n) {  // fewer than E trailing columns
-            float xs = a.x[tail0 + lane];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                acc[r].add_scalar(load_elem<T>(rows[r], tail0 + lane), xs);
-        }
-
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if constexpr (ACC == ACC_F64) {
-                double d = wave_sum((double)acc[r].value());
-                if (lane == 0 && r0 + r < a.m) {
-                    double by = a.beta == 0.f ? 0.0 : (double)a.beta * (double)a.y[r0 + r];
-                    a.y[r0 + r] = (float)((double)a.alpha * d + by);
-                }
-            } else if constexpr (ACC == ACC_COMP) {
-                Pair p = wave_sum(acc[r].value());
-                if (lane == 0 && r0 + r < a.m)
-                    store_row<ACC>(a.y, r0 + r, a.alpha, a.beta, p.s + p.c);
-            } else {
-                float d = wave_sum(acc[r].value());
-                if (lane == 0 && r0 + r < a.m)
-                    store_row<ACC>(a.y, r0 + r, a.alpha, a.beta, d);
-            }
-        }
-    }
+    for (int64_t r0 = gw * R; r0 < a.m; r0 += nw * R)  // wave-uniform loop
+        gemv_row_group<T, ACC, VB, R, U>(a.A, a.x, a.y, a.m, a.n, a.lda, a.nvec, a.alpha, a.beta, r0, lane);
 }
 
 template <class T, int ACC, int VB, int R>

@@ -58,6 +58,57 @@ struct GemvArgs {
     float beta;
 };
 
+// ---- batched form ----------------------------------------------------------
+
+enum Kind { KIND_ASUM = 0, KIND_DOT = 1, KIND_GEMV = 2 };
+
+// One problem of a batch, as the kernel reads it.  Reductions: the element
+// range is head scalars, nvec vectors of the batch's vector width (or, when
+// vec == 0, nvec = n single elements), then the scalar tail.  gemv: rows of
+// lda elements, nvec vectors per row when vec != 0.
+struct BatchProblem {
+    int32_t kind;
+    int32_t vec;        // 1: vector loads; 0: element loads
+    int32_t ntiles;
+    int32_t pad;
+    int64_t n;          // elements (reductions) or columns (gemv)
+    int64_t m;          // gemv rows
+    int64_t lda;
+    int64_t head;
+    int64_t nvec;
+    int64_t slot_base;  // first partial slot of this problem
+    const void *a;
+    const void *b;
+    void *out;
+    float alpha;
+    float beta;
+};
+
+// One tile: vectors (or elements) [begin, begin + len) of a reduction, or
+// rows [begin, begin + len) of a gemv.
+struct BatchTile {
+    int32_t problem;
+    int32_t index;      // tile number within its problem
+    int64_t begin;
+    int64_t len;
+};
+
+// Device state of a batch: [next tile | finished work-groups] counters, one
+// arrival counter per problem, and 16-byte partial slots.
+struct BatchArgs {
+    const BatchProblem *probs;
+    const BatchTile *tiles;
+    unsigned *counters;   // [0] next tile, [1] work-groups done
+    unsigned *pcount;     // per problem: tiles finished
+    char *slots;
+    int64_t ntiles;
+    int32_t result_f64;
+};
+
+const void *batch_kernel_f32(int acc, int vec_bytes, int unroll);
+const void *batch_kernel_bf16(int acc, int vec_bytes, int unroll);
+const void *batch_kernel_f16(int acc, int vec_bytes, int unroll);
+
 // Kernel tables (nullptr where a combination is not built).
 const void *reduce_kernel(int dtype, int op, int acc, int vec_bytes, int unroll);
 const void *scal_kernel(int vec_bytes, int unroll);

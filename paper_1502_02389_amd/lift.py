@@ -44,11 +44,31 @@ class lift_knobs(ctypes.Structure):
         ("unroll", ctypes.c_int32),
         ("rows_per_wave", ctypes.c_int32),
         ("split", ctypes.c_int64),
+        ("wg_per_cu", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
-def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0):
-    return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split)
+def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0, wg_per_cu=0):
+    return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split, wg_per_cu, 0)
+
+
+LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV = 0, 1, 2
+
+
+class lift_problem(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("lda", ctypes.c_int64),
+        ("a", ctypes.c_void_p),
+        ("b", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("alpha", ctypes.c_float),
+        ("beta", ctypes.c_float),
+    ]
 
 
 _LIB = None
@@ -72,6 +92,13 @@ SIGNATURES = {
     "lift_last_hip_error": (_i32, []),
     "lift_version": (ctypes.c_char_p, []),
     "lift_time_next_launch": (_i32, [_vp, _vp]),
+    "lift_batch_create": (_i32, [ctypes.POINTER(lift_problem), ctypes.c_int32, _i32, _i32, _i32, _kp,
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "lift_batch_run": (_i32, [_vp, _vp]),
+    "lift_batch_capture": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_void_p)]),
+    "lift_batch_info": (_i32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_int64)]),
+    "lift_batch_destroy": (None, [_vp]),
 }
 
 
@@ -159,6 +186,30 @@ def lift_version():
 
 def lift_time_next_launch(start, stop):
     return _lib().lift_time_next_launch(start, stop)
+
+
+def lift_batch_create(probs, count, storage, acc, rt, knobs, out):
+    """probs: ctypes array of lift_problem; out: ctypes.c_void_p receiving the handle."""
+    return _lib().lift_batch_create(probs, count, storage, acc, rt, _kptr(knobs), ctypes.byref(out))
+
+
+def lift_batch_run(batch, stream=0):
+    return _lib().lift_batch_run(batch, stream)
+
+
+def lift_batch_capture(batch, stream, exec_out):
+    """exec_out: ctypes.c_void_p receiving the hipGraphExec_t."""
+    return _lib().lift_batch_capture(batch, stream, ctypes.byref(exec_out))
+
+
+def lift_batch_info(batch):
+    t, g, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    st = _lib().lift_batch_info(batch, ctypes.byref(t), ctypes.byref(g), ctypes.byref(b))
+    return st, t.value, g.value, b.value
+
+
+def lift_batch_destroy(batch):
+    _lib().lift_batch_destroy(batch)
 
 
 class HipEvents:
@@ -349,3 +400,128 @@ def gemv(alpha, A, x, beta, y, acc="f32", knobs=None, lda=None):
     _ok(lift_gemv_ex(m, n, float(alpha), _dtype_code(A.dtype), A.data_ptr(), lda, x.data_ptr(),
                      float(beta), y.data_ptr(), accc, knobs, s), "lift_gemv")
     return y
+
+
+# ---------------------------------------------------------------- batched form
+
+
+class Batch:
+    """Many asum / dot / gemv problems run as one persistent kernel.
+
+    ``problems`` is a list of tuples:
+      ("asum", x)                       -> result written to a 0-d tensor
+      ("dot", x, y)
+      ("gemv", alpha, A, x, beta, y)    -> y updated in place (A is (m, lda))
+    All x / y / A of reductions and A of gemv share one storage dtype; gemv x
+    and y are float32.  The tensors are kept alive by the batch; results
+    live in ``self.results`` (one 0-d tensor per reduction, None for gemv).
+    """
+
+    def __init__(self, problems, acc="f32", result_dtype=None, knobs=None, device=None):
+        torch = _torch()
+        self._hip = None
+        self.handle = ctypes.c_void_p()
+        self.keep = []
+        self.results = []
+        dev = torch.device(device) if device is not None else None
+        storage = None
+        arr = (lift_problem * max(1, len(problems)))()
+        rdt = result_dtype or torch.float32
+        for i, pr in enumerate(problems):
+            kind = pr[0]
+            q = arr[i]
+            if kind in ("asum", "dot"):
+                x = pr[1]
+                _check_tensor(x, "x", (torch.float32, torch.bfloat16, torch.float16))
+                dev = dev or x.device
+                storage = storage or x.dtype
+                if x.dtype != storage:
+                    raise TypeError("every problem of a batch uses one storage dtype")
+                res = torch.zeros((), dtype=rdt, device=dev)
+                q.kind = LIFT_KIND_ASUM if kind == "asum" else LIFT_KIND_DOT
+                q.n = x.numel()
+                q.a = x.data_ptr() or None
+                q.out = res.data_ptr()
+                self.keep.append(x)
+                if kind == "dot":
+                    y = pr[2]
+                    _check_tensor(y, "y", (storage,))
+                    if y.numel() != x.numel():
+                        raise ValueError("dot operands differ in length")
+                    q.b = y.data_ptr() or None
+                    self.keep.append(y)
+                self.results.append(res)
+            elif kind == "gemv":
+                alpha, A, x, beta, y = pr[1:6]
+                _check_tensor(A, "A", (torch.float32, torch.bfloat16, torch.float16))
+                _check_tensor(x, "x", (torch.float32,))
+                _check_tensor(y, "y", (torch.float32,))
+                dev = dev or A.device
+                storage = storage or A.dtype
+                if A.dtype != storage:
+                    raise TypeError("every problem of a batch uses one storage dtype")
+                q.kind = LIFT_KIND_GEMV
+                q.m, q.n, q.lda = A.shape[0], x.numel(), A.shape[1]
+                q.a, q.b, q.out = A.data_ptr() or None, x.data_ptr() or None, y.data_ptr() or None
+                q.alpha, q.beta = float(alpha), float(beta)
+                self.keep += [A, x, y]
+                self.results.append(None)
+            else:
+                raise ValueError(f"unknown problem kind {kind!r}")
+        storage = storage or torch.float32
+        self.device = dev or torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            st = lift_batch_create(arr, len(problems), _dtype_code(storage), ACC[acc] if isinstance(acc, str)
+                                   else int(acc), _dtype_code(rdt), knobs, self.handle)
+        _ok(st, "lift_batch_create")
+        _, self.tiles, self.grid, self.bytes = lift_batch_info(self.handle)
+        self.graphs = []
+
+    def run(self, stream=None):
+        s = _stream_handle(self.device) if stream is None else stream
+        _ok(lift_batch_run(self.handle, s), "lift_batch_run")
+
+    def capture(self, stream):
+        """Capture one run into a HIP graph on `stream` (a non-default
+        torch.cuda.Stream or raw handle); returns a replayable GraphRun."""
+        h = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        ex = ctypes.c_void_p()
+        _ok(lift_batch_capture(self.handle, h, ex), "lift_batch_capture")
+        g = GraphRun(ex.value)
+        self.graphs.append(g)
+        return g
+
+    def close(self):
+        for g in self.graphs:
+            g.close()
+        self.graphs = []
+        if self.handle:
+            lift_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GraphRun:
+    """An instantiated HIP graph (hipGraphExec_t) replayed with hipGraphLaunch."""
+
+    def __init__(self, exec_handle):
+        self.exec = exec_handle
+        self._hip = ctypes.CDLL("libamdhip64.so")
+        self._hip.hipGraphLaunch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self._hip.hipGraphExecDestroy.argtypes = [ctypes.c_void_p]
+
+    def launch(self, stream):
+        h = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        err = self._hip.hipGraphLaunch(self.exec, h)
+        if err != 0:
+            raise RuntimeError(f"hipGraphLaunch failed ({err})")
+
+    def close(self):
+        if self.exec:
+            self._hip.hipGraphExecDestroy(self.exec)
+            self.exec = None

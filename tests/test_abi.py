@@ -61,10 +61,13 @@ def test_enum_values_match_header():
         assert getattr(B, name) == value
 
 
-def test_knobs_struct_layout():
-    # int32 x4 then int64: 24 bytes, split at offset 16
-    assert ctypes.sizeof(B.lift_knobs) == 24
-    assert B.lift_knobs.split.offset == 16
+def test_struct_layouts():
+    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, int32 reserved
+    assert ctypes.sizeof(B.lift_knobs) == 32
+    assert B.lift_knobs.split.offset == 16 and B.lift_knobs.wg_per_cu.offset == 24
+    # lift_problem: int32 kind, int32 reserved, int64 m, n, lda, 3 pointers, 2 floats
+    assert ctypes.sizeof(B.lift_problem) == 64
+    assert B.lift_problem.a.offset == 32 and B.lift_problem.alpha.offset == 56
 
 
 def test_workspace_size_and_version():
@@ -164,3 +167,58 @@ def test_time_next_launch_argument_rules():
     assert L.lift_time_next_launch(0x1000, 0) == L.LIFT_EINVAL
     assert L.lift_time_next_launch(0, 0x1000) == L.LIFT_EINVAL
     assert L.lift_time_next_launch(0, 0) == L.LIFT_OK
+
+
+def _batch_status(probs, storage=0, acc=0, rt=0, knobs=None, count=None):
+    arr = (B.lift_problem * max(1, len(probs)))()
+    for i, p in enumerate(probs):
+        for k, v in p.items():
+            setattr(arr[i], k, v)
+    h = ctypes.c_void_p()
+    st = L.lift_batch_create(arr, len(probs) if count is None else count, storage, acc, rt, knobs, h)
+    assert not h.value  # nothing is created on error (and no GPU here)
+    return st
+
+
+@cpu_only
+def test_batch_rejects_bad_problems():
+    ok_red = dict(kind=0, n=16, a=X, out=R)
+    assert _batch_status([dict(kind=7, n=4, a=X, out=R)]) == L.LIFT_EINVAL            # kind
+    assert _batch_status([dict(ok_red, reserved=1)]) == L.LIFT_EINVAL                  # reserved
+    assert _batch_status([dict(ok_red, n=-1)]) == L.LIFT_EINVAL                        # n < 0
+    assert _batch_status([dict(ok_red, a=0)]) == L.LIFT_EINVAL                         # null x
+    assert _batch_status([dict(ok_red, out=0)]) == L.LIFT_EINVAL                       # null result
+    assert _batch_status([dict(ok_red, a=X + 2)]) == L.LIFT_EINVAL                     # misaligned
+    assert _batch_status([dict(kind=1, n=16, a=X, out=R)]) == L.LIFT_EINVAL            # dot without y
+    assert _batch_status([ok_red, dict(ok_red, a=Y)]) == L.LIFT_EINVAL                 # two results alias
+    assert _batch_status([ok_red, dict(kind=0, n=16, a=Y, out=X + 8)]) == L.LIFT_EINVAL  # result in an input
+    gemv = dict(kind=2, m=8, n=16, lda=16, a=X, b=Y, out=R, alpha=1.0, beta=0.5)
+    assert _batch_status([dict(gemv, lda=15)]) == L.LIFT_EINVAL                        # lda < n
+    assert _batch_status([dict(gemv, m=-1)]) == L.LIFT_EINVAL
+    assert _batch_status([dict(gemv, b=0)]) == L.LIFT_EINVAL                           # null x
+    assert _batch_status([dict(gemv, out=X + 64)]) == L.LIFT_EINVAL                    # y inside A
+    assert _batch_status([ok_red], storage=L.LIFT_F64) == L.LIFT_EINVAL
+    assert _batch_status([ok_red], acc=5) == L.LIFT_EINVAL
+    assert _batch_status([ok_red], rt=L.LIFT_F16) == L.LIFT_EINVAL
+    assert _batch_status([ok_red], knobs=B.knobs(wg_per_cu=-1)) == L.LIFT_EINVAL
+    assert _batch_status([ok_red], knobs=B.knobs(vec_bytes=2), storage=L.LIFT_BF16) == L.LIFT_EUNSUPPORTED
+    assert _batch_status([ok_red], count=-1) == L.LIFT_EINVAL
+    k = B.knobs()
+    k.reserved = 3
+    assert _batch_status([ok_red], knobs=k) == L.LIFT_EINVAL
+
+
+@cpu_only
+def test_batch_null_handles():
+    assert L.lift_batch_run(None) == L.LIFT_EINVAL
+    st, *_ = L.lift_batch_info(None)
+    assert st == L.LIFT_EINVAL
+    L.lift_batch_destroy(None)   # no-op
+    h = ctypes.c_void_p()
+    assert B._lib().lift_batch_create(None, 0, 0, 0, 0, None, None) == L.LIFT_EINVAL
+
+
+@cpu_only
+def test_batch_valid_plan_without_gpu_reports_hip_error():
+    assert _batch_status([dict(kind=0, n=16, a=X, out=R),
+                          dict(kind=2, m=8, n=16, lda=16, a=Y, b=WS, out=R + 256, alpha=1.0, beta=0.5)]) == L.LIFT_EHIP
