@@ -319,6 +319,11 @@ def forms(L, W, dev, stream):
         del xs, ys
         torch.cuda.empty_cache()
 
+    # batched form (4096 reductions + 256 gemv) vs the same problems per call
+    for storage in ("f32", "bf16"):
+        out.update(batch_form(L, W, dev, stream, storage))
+        torch.cuda.empty_cache()
+
     # bf16 gemv 16384^2 (A 512 MiB: larger than the Infinity Cache by itself)
     A, x, y, alpha, beta = W.config4_gemv()
     size = A.shape[0]
@@ -331,6 +336,115 @@ def forms(L, W, dev, stream):
                                     yd.data_ptr(), acc, None, sh) == 0
         rec(f"gemv_bf16_{acc_name}_{size}", _time_calls(cg, 1, stream, reps=20), nb, fb)
     return out
+
+
+def batch_form(L, W, dev, stream, storage):
+    """Config-5 batch: one persistent launch vs per-call kernels (eager and
+    captured in a graph) over the same problems.  Values are drawn on the GPU
+    (throughput only; parity is checked by the tests)."""
+    import torch
+
+    lib = L.library()
+    spec = W.config5_shapes()
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16}[storage]
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    probs = []
+    for kind, n in zip(spec.red_kind, spec.red_len):
+        x = (torch.rand(n, generator=g, device=dev) * 2 - 1).to(dt)
+        probs.append(("dot", x, (torch.rand(n, generator=g, device=dev) * 2 - 1).to(dt)) if kind == "dot"
+                     else ("asum", x))
+    for m, n in spec.gemv_mn:
+        probs.append(("gemv", 1.0, torch.randn((m, n), generator=g, device=dev).to(dt),
+                      torch.randn(n, generator=g, device=dev), 0.5, torch.randn(m, generator=g, device=dev)))
+    tuned = None
+    try:
+        from paper_1502_02389_amd import tune
+        tuned = tune.lookup("batch", storage, "f32", 0)
+    except Exception:
+        tuned = None
+    b = L.Batch(probs, knobs=tuned)
+    fp32_bytes = sum(4 * n * (2 if k == "dot" else 1) + 4 for k, n in zip(spec.red_kind, spec.red_len)) + \
+        sum(4 * m * n + 4 * n + 8 * m for m, n in spec.gemv_mn)
+    ev = L.HipEvents(2)
+    times = []
+    for i in range(7):
+        if i >= 2:
+            lib.lift_time_next_launch(ev.events[0], ev.events[1])
+        b.run()
+        torch.cuda.synchronize()
+        if i >= 2:
+            times.append(ev.elapsed_ms(0, 1) * 1e3)
+    ev.close()
+    batch_us = statistics.median(times)
+
+    # the same problems as per-call plain kernels, back to back on one stream
+    ws = L.workspace(dev)
+    code = {"f32": L.LIFT_F32, "bf16": L.LIFT_BF16}[storage]
+    res = torch.zeros(len(probs), dtype=torch.float32, device=dev)
+    calls = []
+    for i, pr in enumerate(probs):
+        if pr[0] == "asum":
+            calls.append(("a", pr[1].numel(), pr[1].data_ptr(), 0, res.data_ptr() + 4 * i))
+        elif pr[0] == "dot":
+            calls.append(("d", pr[1].numel(), pr[1].data_ptr(), pr[2].data_ptr(), res.data_ptr() + 4 * i))
+        else:
+            A, x, y = pr[2], pr[3], pr[5]
+            calls.append(("g", A.shape[0], A.shape[1], A.data_ptr(), x.data_ptr(), y.data_ptr()))
+
+    def per_call(sh):
+        for c in calls:
+            if c[0] == "a":
+                st = lib.lift_asum_ex(c[1], code, c[2], 0, L.LIFT_F32, c[4], ws.data_ptr(), ws.numel(), None, sh)
+            elif c[0] == "d":
+                st = lib.lift_dot_ex(c[1], code, c[2], c[3], 0, L.LIFT_F32, c[4], ws.data_ptr(), ws.numel(), None, sh)
+            else:
+                st = lib.lift_gemv_ex(c[1], c[2], 1.0, code, c[3], c[2], c[4], 0.5, c[5], 0, None, sh)
+            if st != 0:
+                raise L.LiftError(st, "per-call baseline")
+
+    per_call(stream.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    per_call(stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eager_us = e0.elapsed_time(e1) * 1e3
+
+    graph_us = None
+    try:
+        cg = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(cg, stream=side):
+                per_call(torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        cg.replay()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        cg.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        graph_us = e0.elapsed_time(e1) * 1e3
+        del cg
+    except Exception as exc:  # report, do not fail the bench
+        log("per-call graph capture failed:", exc)
+
+    bb = b.bytes
+    rec = {"problems": len(probs), "tiles": b.tiles, "grid": b.grid, "bytes": bb, "fp32_bytes": fp32_bytes,
+           "batch_us": round(batch_us, 1), "GB_s": round(bb / (batch_us * 1e-6) / 1e9, 1),
+           "frac_of_peak": round(bb / (batch_us * 1e-6) / 1e9 / PEAK_GBS, 4),
+           "fp32_equiv_GB_s": round(fp32_bytes / (batch_us * 1e-6) / 1e9, 1),
+           "per_call_eager_us": round(eager_us, 1),
+           "per_call_eager_GB_s": round(bb / (eager_us * 1e-6) / 1e9, 1),
+           "per_call_graph_us": round(graph_us, 1) if graph_us else None,
+           "per_call_graph_GB_s": round(bb / (graph_us * 1e-6) / 1e9, 1) if graph_us else None,
+           "knobs": "tuned" if tuned is not None else "default"}
+    log("form batch", storage, rec)
+    b.close()
+    return {f"batch_{storage}_config5": rec}
 
 
 if __name__ == "__main__":

@@ -94,6 +94,13 @@ def save_cache(entries: dict, meta: dict, path: str | None = None):
 
 def grid(op: str, storage: str, quick: bool = False):
     eb = STORAGE_BYTES[storage]
+    if op == "batch":
+        blocks = (256, 512) if quick else (128, 256, 512, 1024)
+        vecs = (16,) if quick else tuple(v for v in (8, 16) if v >= eb)
+        splits = (1 << 15, 1 << 16, 1 << 17) if quick else (1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
+        for b, v, u, s, w in itertools.product(blocks, vecs, (2, 4, 8), splits, (1, 2, 4, 8)):
+            yield dict(block=b, vec_bytes=v, unroll=u, split=s, wg_per_cu=w)
+        return
     if op == "gemv":
         blocks = (64, 256, 1024) if quick else (64, 128, 256, 512, 1024)
         vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)
@@ -109,6 +116,56 @@ def grid(op: str, storage: str, quick: bool = False):
 
 
 # ---------------------------------------------------------------- timing
+
+
+class BatchOperands:
+    """The batched workload (reductions + gemv problems), drawn on the GPU;
+    each knob point plans its own batch over the same tensors."""
+
+    def __init__(self, storage, seed=5):
+        import torch
+
+        import workloads as W
+
+        self.op, self.storage = "batch", storage
+        dev = torch.device("cuda:0")
+        spec = W.config5_shapes()
+        dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[storage]
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed)
+        self.problems = []
+        for kind, n in zip(spec.red_kind, spec.red_len):
+            x = (torch.rand(n, generator=g, device=dev) * 2 - 1).to(dt)
+            if kind == "dot":
+                self.problems.append(("dot", x, (torch.rand(n, generator=g, device=dev) * 2 - 1).to(dt)))
+            else:
+                self.problems.append(("asum", x))
+        for m, n in spec.gemv_mn:
+            self.problems.append(("gemv", 1.0, torch.randn((m, n), generator=g, device=dev).to(dt),
+                                  torch.randn(n, generator=g, device=dev), 0.5,
+                                  torch.randn(m, generator=g, device=dev)))
+        self.bytes = None
+        self.sets = 1
+
+    def time_us(self, acc, k, reps=5, trials=1):
+        import torch
+
+        b = B.Batch(self.problems, acc=acc, knobs=k)
+        self.bytes = b.bytes
+        ev = B.HipEvents(2)
+        best = float("inf")
+        try:
+            for i in range(reps + 2):
+                if i >= 2:
+                    B.lift_time_next_launch(ev.events[0], ev.events[1])
+                b.run()
+                torch.cuda.synchronize()
+                if i >= 2:
+                    best = min(best, ev.elapsed_ms(0, 1) * 1e3)
+        finally:
+            ev.close()
+            b.close()
+        return best
 
 
 class Operands:
@@ -180,8 +237,8 @@ class Operands:
 
 def tune_one(op, storage, acc, elements=None, m=None, n=None, quick=False, log=None):
     """Search the grid for one call shape; returns (best entry, all results)."""
-    ops = Operands(op, storage, elements, m, n)
-    accc = B.ACC[acc]
+    ops = BatchOperands(storage) if op == "batch" else Operands(op, storage, elements, m, n)
+    accc = acc if op == "batch" else B.ACC[acc]
     results = []
     for kn in grid(op, storage, quick):
         k = B.knobs(**kn)
@@ -223,7 +280,7 @@ def main(argv=None):
                 if op == "scal" and (storage != "f32" or acc != "f32"):
                     continue
                 shapes = ([tuple(int(v) for v in s.split("x")) for s in args.gemv.split(",")] if op == "gemv"
-                          else [(1 << int(s),) for s in args.sizes.split(",")])
+                          else [(0,)] if op == "batch" else [(1 << int(s),) for s in args.sizes.split(",")])
                 for shp in shapes:
                     if op == "gemv":
                         best, res = tune_one(op, storage, acc, m=shp[0], n=shp[1], quick=args.quick,
