@@ -247,8 +247,8 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
         return LIFT_EINVAL;
     Knobs k;
     Knobs def = DEF_REDUCE;
-    if (eb == 2)
-        def.unroll = 4;  // 8 elements per 16-byte load already; more only adds registers
+    if (eb == 2 && op == OP_DOT)
+        def.unroll = 4;  // two 16-bit streams: 4 loads of each in flight measured best
     lift_status st = resolve(knobs, def, eb, &k);
     if (st != LIFT_OK)
         return st;

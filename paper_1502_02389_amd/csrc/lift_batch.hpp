@@ -43,6 +43,7 @@ __device__ __forceinline__ typename BlockT<ACC>::type tile_lane_value(const Batc
             if constexpr (OP == OP_DOT)
                 vy[k] = load_stream<VB>(yv, base + t + k * B);
         }
+        loads_in_flight();
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             float fx[E], fy[E];

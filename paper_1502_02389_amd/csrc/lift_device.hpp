@@ -47,6 +47,11 @@ __device__ __forceinline__ typename Vec<VB>::type load_stream(const void *base, 
     return __builtin_nontemporal_load(reinterpret_cast<const typename Vec<VB>::type *>(base) + i);
 }
 
+// Scheduling fence after a group of independent loads: keeps the compiler
+// from sinking each load next to its first use (which would leave one load
+// in flight per wave and make the stream latency-bound).
+__device__ __forceinline__ void loads_in_flight() { __builtin_amdgcn_sched_barrier(0); }
+
 template <int VB>
 __device__ __forceinline__ void store_stream(void *base, int64_t i, typename Vec<VB>::type v)
 {

@@ -142,6 +142,7 @@ __device__ __forceinline__ void gemv_row_group(const void *A, const float *x, fl
 #pragma unroll
             for (int k = 0; k < U; ++k)
                 va[r][k] = load_stream<VB>(rows[r], base + lane + 64 * k);
+        loads_in_flight();
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll

@@ -269,6 +269,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
             if constexpr (OP == OP_DOT)
                 vy[k] = load_stream<VB>(yv, base + t + k * B);
         }
+        loads_in_flight();
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             float fx[E], fy[E];

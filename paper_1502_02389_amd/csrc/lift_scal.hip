@@ -43,6 +43,7 @@ __global__ void __launch_bounds__(1024) scal_kernel_t(ScalArgs a)
 #pragma unroll
         for (int k = 0; k < U; ++k)
             v[k] = load_stream<VB>(xv, base + t + k * B);
+        loads_in_flight();
 #pragma unroll
         for (int k = 0; k < U; ++k)
             store_stream<VB>(ov, base + t + k * B, scale_vec<VB>(v[k], a.alpha));
