@@ -96,7 +96,8 @@ typedef enum lift_acc {
  * plus the rows handled together by one wavefront in gemv.  A zero field
  * selects the library default for that field. */
 typedef struct lift_knobs {
-    int32_t block;         /* work-group size: 64, 128, 256, 512 or 1024 */
+    int32_t block;         /* work-group size: 64, 128, 256, 512 or 1024
+                              (batched form: at most 512) */
     int32_t vec_bytes;     /* bytes per lane per load: 2 (16-bit storage
                               only), 4, 8 or 16 -- asVector width times the
                               element size */

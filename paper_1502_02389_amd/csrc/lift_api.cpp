@@ -413,6 +413,8 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
         return st;
     if (k.vec_bytes < 4)
         return LIFT_EUNSUPPORTED;  // the batched kernels load at least a dword per lane
+    if (k.block > 512)
+        return LIFT_EUNSUPPORTED;  // built for at most 512 threads (no register spills at 8 loads in flight)
     const int vb = k.vec_bytes;
     const int64_t e = vb / eb;
 
@@ -536,9 +538,12 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     if (he != hipSuccess)
         return hip_fail(he);
 
-    // one allocation: counters | per-problem counters | problems | tiles | slots
+    // one allocation: counters | group counters | per-problem counters |
+    // problems | tiles | slots
     auto up = [](int64_t v) { return (v + 255) / 256 * 256; };
-    const int64_t off_pc = 256;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * k.wg_per_cu, (int64_t)sorted.size()));
+    const int64_t off_gc = 256;
+    const int64_t off_pc = off_gc + up((grid + ARRIVAL_GROUP - 1) / ARRIVAL_GROUP * WS_GROUP_STRIDE);
     const int64_t off_pr = off_pc + up(std::max<int64_t>(count, 1) * 4);
     const int64_t off_ti = off_pr + up(std::max<int64_t>(count, 1) * (int64_t)sizeof(BatchProblem));
     const int64_t off_sl = off_ti + up(std::max<int64_t>((int64_t)sorted.size(), 1) * (int64_t)sizeof(BatchTile));
@@ -561,12 +566,13 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     b->nprobs = count;
     b->bytes = bytes;
     b->block = k.block;
-    b->grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * k.wg_per_cu, b->ntiles));
+    b->grid = grid;
     b->dmem = mem;
     b->kern = kern;
     b->args.probs = (const BatchProblem *)(base + off_pr);
     b->args.tiles = (const BatchTile *)(base + off_ti);
     b->args.counters = (unsigned *)base;
+    b->args.groups = base + off_gc;
     b->args.pcount = (unsigned *)(base + off_pc);
     b->args.slots = base + off_sl;
     b->args.ntiles = b->ntiles;

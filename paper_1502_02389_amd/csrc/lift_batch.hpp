@@ -53,12 +53,35 @@ __device__ __forceinline__ typename BlockT<ACC>::type tile_lane_value(const Batc
             accumulate<T, OP, ACC, E>(acc, fx, fy);
         }
     }
-    for (int64_t i = base + t; i < vend; i += B) {
-        float fx[E], fy[E];
-        decode<T, VB>(load_stream<VB>(xv, i), fx);
-        if constexpr (OP == OP_DOT)
-            decode<T, VB>(load_stream<VB>(yv, i), fy);
-        accumulate<T, OP, ACC, E>(acc, fx, fy);
+    if (base < vend) {
+        // Final partial step: fewer than U vectors per lane.  Every lane loads
+        // U vectors at clamped (in-range) indices so all loads are in flight
+        // without branches; the ones past the end are replaced by zeros, which
+        // leave every sum unchanged.
+        V vx[U], vy[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t i = min(base + t + k * B, vend - 1);
+            vx[k] = load_stream<VB>(xv, i);
+            if constexpr (OP == OP_DOT)
+                vy[k] = load_stream<VB>(yv, i);
+        }
+        loads_in_flight();
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const bool in = base + t + k * B < vend;
+            float fx[E], fy[E];
+            decode<T, VB>(vx[k], fx);
+            if constexpr (OP == OP_DOT)
+                decode<T, VB>(vy[k], fy);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                fx[e] = in ? fx[e] : 0.f;
+                if constexpr (OP == OP_DOT)
+                    fy[e] = in ? fy[e] : 0.f;
+            }
+            accumulate<T, OP, ACC, E>(acc, fx, fy);
+        }
     }
     if (tl.index == 0 && t < p.head) {
         float fy = OP == OP_DOT ? load_elem<T>(p.b, t) : 0.f;
@@ -85,25 +108,31 @@ __device__ __forceinline__ void gemv_tile(const BatchProblem &p, const BatchTile
         gemv_row_group<T, ACC, VB, 1, U>(p.a, x, y, p.m, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
 }
 
-// Next tile for the work-group: thread 0 draws it from the shared counter,
-// everyone reads it after a barrier.  Wave-uniform (scalar) result.
+// Next tile for the work-group: thread 0 draws it from the shared counter
+// (offset by the grid size: work-group b's first tile is b, taken without
+// an atomic, so the launch does not start with every work-group contending
+// for one address); everyone reads it after a barrier.  Wave-uniform result.
 __device__ __forceinline__ int fetch_tile(unsigned *counter, int *s_tile)
 {
     if (threadIdx.x == 0)
-        *s_tile = (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s_tile = (int)gridDim.x +
+                  (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int ti = __builtin_amdgcn_readfirstlane(*s_tile);
     __syncthreads();  // every wave has read s_tile before thread 0 may write it again
     return ti;
 }
 
+// At most 512 threads per work-group: the widest instance (dot, 16-byte
+// loads, 8 in flight) needs about 160 VGPRs, more than a 1024-thread
+// work-group leaves each wave.
 // The loop is written so that its only back edge passes through fetch_tile:
 // no continue / break, and every branch inside it is on a work-group-uniform
 // scalar.  (A loop whose head is thread 0's conditional fetch, re-entered
 // from several places, can be restructured by the compiler into a back edge
 // that reaches the barrier without the fetch, splitting wave 0 around it.)
 template <class T, int ACC, int VB, int U>
-__global__ void __launch_bounds__(1024) batch_kernel(BatchArgs a)
+__global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
 {
     using BT = typename BlockT<ACC>::type;
     using ST = typename SlotT<ACC>::type;
@@ -115,7 +144,7 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchArgs a)
     const int t = threadIdx.x;
     const int64_t B = blockDim.x;
 
-    int ti = fetch_tile(&a.counters[0], &s_tile);
+    int ti = blockIdx.x;  // the grid never exceeds the tile count
     while (ti < a.ntiles) {
         const BatchTile tl = a.tiles[ti];
         const BatchProblem p = a.probs[tl.problem];
@@ -160,13 +189,11 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchArgs a)
         ti = fetch_tile(&a.counters[0], &s_tile);
     }
 
-    // The last work-group out resets the counters for the next launch.
-    if (t == 0) {
-        unsigned prev = __hip_atomic_fetch_add(&a.counters[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == gridDim.x - 1) {
-            __hip_atomic_store(&a.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+    // The last work-group out (two-level arrival) resets the counters for the
+    // next launch; by then no work-group will read the tile counter again.
+    if (t == 0 && arrive(&a.counters[1], a.groups)) {
+        __hip_atomic_store(&a.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -152,15 +152,39 @@ __device__ __forceinline__ void gemv_row_group(const void *A, const float *x, fl
                 acc[r].add(af, xf[k]);
             }
     }
-    for (int64_t v = base + lane; v < nvec; v += 64) {
-        float xf[E];
-        load_x<E>(x, v, xf);
+    if (base < nvec) {
+        // Final partial step: fewer than U vectors per lane, loaded at clamped
+        // indices so all are in flight; those past the row end become zeros.
+        float xf[U][E];
+        V va[R][U];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float af[E];
-            decode<T, VB>(load_stream<VB>(rows[r], v), af);
-            acc[r].add(af, xf);
+        for (int k = 0; k < U; ++k) {
+            const int64_t v = min(base + lane + 64 * k, nvec - 1);
+            load_x<E>(x, v, xf[k]);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                va[r][k] = load_stream<VB>(rows[r], v);
         }
+        loads_in_flight();
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const bool in = base + lane + 64 * k < nvec;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                xf[k][e] = in ? xf[k][e] : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const bool in = base + lane + 64 * k < nvec;
+                float af[E];
+                decode<T, VB>(va[r][k], af);
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    af[e] = in ? af[e] : 0.f;
+                acc[r].add(af, xf[k]);
+            }
     }
     if (tail0 + lane < n) {  // fewer than E trailing columns
         float xs = x[tail0 + lane];

@@ -11,11 +11,18 @@ enum Dtype { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2, DT_F64 = 3 };
 enum Op { OP_ASUM = 0, OP_DOT = 1 };
 enum Acc { ACC_F32 = 0, ACC_COMP = 1, ACC_F64 = 2 };
 
-// Workspace layout: a 32-bit arrival counter in the first 256 bytes, then
-// one 16-byte partial slot per work-group.
-constexpr int64_t WS_HEADER = 256;
-constexpr int64_t WS_SLOT = 16;
+// Workspace layout: the global arrival counter in the first 256 bytes; one
+// group arrival counter per ARRIVAL_GROUP work-groups, each in its own
+// 64-byte line; then one 16-byte partial slot per work-group.  Arrivals are
+// counted in two levels because agent-scope atomics on a single address
+// serialize (about 10 ns each on MI355X) when every work-group finishes at
+// once.
 constexpr int32_t MAX_WORKGROUPS = 8192;
+constexpr int32_t ARRIVAL_GROUP = 16;
+constexpr int64_t WS_GROUPS = 256;                      // offset of the group counters
+constexpr int64_t WS_GROUP_STRIDE = 64;
+constexpr int64_t WS_HEADER = WS_GROUPS + (MAX_WORKGROUPS / ARRIVAL_GROUP) * WS_GROUP_STRIDE;
+constexpr int64_t WS_SLOT = 16;
 
 // reduce(add, 0) . map(abs) over x, or reduce(add, 0) . map(mult) . zip(x, y).
 // Elements [0, head) are scalars before the first VB-aligned address; then
@@ -93,12 +100,16 @@ struct BatchTile {
     int64_t len;
 };
 
-// Device state of a batch: [next tile | finished work-groups] counters, one
-// arrival counter per problem, and 16-byte partial slots.
+// Device state of a batch: [next tile | finished work-groups] counters, the
+// group counters of the two-level arrival of finished work-groups, one
+// arrival counter per problem, and 16-byte partial slots.  Work-group b
+// starts with tile b; the next-tile counter hands out tiles from the grid
+// size on.
 struct BatchArgs {
     const BatchProblem *probs;
     const BatchTile *tiles;
-    unsigned *counters;   // [0] next tile, [1] work-groups done
+    unsigned *counters;   // [0] next tile (minus grid size), [1] work-groups done
+    char *groups;         // ceil(grid / ARRIVAL_GROUP) counters, WS_GROUP_STRIDE apart
     unsigned *pcount;     // per problem: tiles finished
     char *slots;
     int64_t ntiles;

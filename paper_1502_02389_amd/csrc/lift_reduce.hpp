@@ -12,16 +12,17 @@
 //
 // term(a) = |a| (asum) or a_x * a_y (dot, zip fused into the load).  The
 // final reduce-seq o join runs in the same launch: every work-group stores
-// its partial, then takes a ticket from an agent-scope counter; the one that
-// draws the last ticket folds all partials in work-group order and writes
-// the result, then resets the counter for the next call.  No float atomics
+// its partial, then counts in on agent-scope arrival counters (two levels,
+// see arrive()); the one that arrives last folds all partials in
+// work-group order and writes the result, then resets the counter for the
+// next call.  No float atomics
 // and no inter-work-group waiting, so the result is deterministic and the
 // grid always drains.
 //
 // Cross-XCD visibility without cache maintenance: the partials are written
 // and read with agent-scope atomic stores / loads, which gfx950 performs
-// device-coherently (write-through / miss in the per-XCD L2), and the ticket
-// is only taken once the partial's store has completed.  An agent-scope
+// device-coherently (write-through / miss in the per-XCD L2), and a
+// work-group counts in only once its partial's store has completed.  An agent-scope
 // release/acquire fence would instead write back and invalidate the whole
 // L2 of the XCD in every work-group.
 #pragma once
@@ -198,6 +199,26 @@ __device__ __forceinline__ Pair load_coherent<Pair>(const char *p)
                                                       __HIP_MEMORY_SCOPE_AGENT));
 }
 
+// Two-level arrival of this work-group (called by one thread, after its
+// partial's store has completed).  Work-group b counts in on the group
+// counter at group_base + (b / ARRIVAL_GROUP) * WS_GROUP_STRIDE; the last of
+// a group resets that counter and counts the group in on `global`.  Returns
+// true in the one work-group that arrives last overall; by then every
+// partial is stored.  The caller resets `global`.
+__device__ __forceinline__ bool arrive(unsigned *global, char *group_base)
+{
+    const unsigned g = blockIdx.x / ARRIVAL_GROUP;
+    const unsigned groups = (gridDim.x + ARRIVAL_GROUP - 1) / ARRIVAL_GROUP;
+    const unsigned size = min((unsigned)ARRIVAL_GROUP, gridDim.x - g * ARRIVAL_GROUP);
+    unsigned *gc = reinterpret_cast<unsigned *>(group_base + g * WS_GROUP_STRIDE);
+    unsigned prev = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev != size - 1)
+        return false;
+    __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    prev = __hip_atomic_fetch_add(global, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return prev == groups - 1;
+}
+
 template <class S>
 __device__ __forceinline__ void write_result(void *result, int f64, S v)
 {
@@ -280,12 +301,35 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
         }
     }
     // the last, partial step of this work-group
-    for (int64_t i = base + t; i < vend; i += B) {
-        float fx[E], fy[E];
-        decode<T, VB>(load_stream<VB>(xv, i), fx);
-        if constexpr (OP == OP_DOT)
-            decode<T, VB>(load_stream<VB>(yv, i), fy);
-        accumulate<T, OP, ACC, E>(acc, fx, fy);
+    if (base < vend) {
+        // Final partial step: fewer than U vectors per lane.  Every lane loads
+        // U vectors at clamped (in-range) indices so all loads are in flight
+        // without branches; the ones past the end are replaced by zeros, which
+        // leave every sum unchanged.
+        V vx[U], vy[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t i = min(base + t + k * B, vend - 1);
+            vx[k] = load_stream<VB>(xv, i);
+            if constexpr (OP == OP_DOT)
+                vy[k] = load_stream<VB>(yv, i);
+        }
+        loads_in_flight();
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const bool in = base + t + k * B < vend;
+            float fx[E], fy[E];
+            decode<T, VB>(vx[k], fx);
+            if constexpr (OP == OP_DOT)
+                decode<T, VB>(vy[k], fy);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                fx[e] = in ? fx[e] : 0.f;
+                if constexpr (OP == OP_DOT)
+                    fy[e] = in ? fy[e] : 0.f;
+            }
+            accumulate<T, OP, ACC, E>(acc, fx, fy);
+        }
     }
     // scalar head (work-group 0) and tail (last work-group), fewer than E each
     if (blockIdx.x == 0 && t < a.head) {
@@ -306,15 +350,13 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
         return;
     }
 
-    unsigned *ticket = reinterpret_cast<unsigned *>(a.ws);
     char *slots = reinterpret_cast<char *>(a.ws) + WS_HEADER;  // 16-byte slots
     if (t == 0) {
         store_coherent(slots + (int64_t)blockIdx.x * WS_SLOT, to_slot<ACC>(wg));
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev == gridDim.x - 1);
+        last = arrive(reinterpret_cast<unsigned *>(a.ws), reinterpret_cast<char *>(a.ws) + WS_GROUPS);
     }
     __syncthreads();
     if (!last)
@@ -326,7 +368,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     v = block_sum<ST>(v, lds_final);
     if (t == 0) {
         write_result(a.result, a.result_f64, v);
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(reinterpret_cast<unsigned *>(a.ws), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -95,7 +95,7 @@ def save_cache(entries: dict, meta: dict, path: str | None = None):
 def grid(op: str, storage: str, quick: bool = False):
     eb = STORAGE_BYTES[storage]
     if op == "batch":
-        blocks = (256, 512) if quick else (128, 256, 512, 1024)
+        blocks = (256, 512) if quick else (128, 256, 512)
         vecs = (16,) if quick else tuple(v for v in (8, 16) if v >= eb)
         splits = (1 << 15, 1 << 16, 1 << 17) if quick else (1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
         for b, v, u, s, w in itertools.product(blocks, vecs, (2, 4, 8), splits, (1, 2, 4, 8)):

@@ -72,6 +72,7 @@ def test_struct_layouts():
 
 def test_workspace_size_and_version():
     assert L.lift_workspace_bytes() >= 256 + 16 * L.lift_max_workgroups()
+    assert (L.lift_workspace_bytes() - 16 * L.lift_max_workgroups()) % 256 == 0
     assert L.lift_max_workgroups() >= 1024
     assert "gfx950" in L.lift_version()
     assert L.lift_status_string(L.LIFT_EINVAL) == "invalid argument"
@@ -203,6 +204,7 @@ def test_batch_rejects_bad_problems():
     assert _batch_status([ok_red], knobs=B.knobs(wg_per_cu=-1)) == L.LIFT_EINVAL
     assert _batch_status([ok_red], knobs=B.knobs(vec_bytes=2), storage=L.LIFT_BF16) == L.LIFT_EUNSUPPORTED
     assert _batch_status([ok_red], count=-1) == L.LIFT_EINVAL
+    assert _batch_status([ok_red], knobs=B.knobs(block=1024)) == L.LIFT_EUNSUPPORTED
     k = B.knobs()
     k.reserved = 3
     assert _batch_status([ok_red], knobs=k) == L.LIFT_EINVAL

@@ -127,7 +127,7 @@ def test_batch_degenerate_problems(gpu_device):
 
 
 KNOBS = [dict(), dict(block=64, vec_bytes=4, unroll=1, split=256, wg_per_cu=1),
-         dict(block=1024, vec_bytes=16, unroll=8, split=1 << 18, wg_per_cu=4),
+         dict(block=512, vec_bytes=16, unroll=8, split=1 << 18, wg_per_cu=4),
          dict(block=256, vec_bytes=8, unroll=2, split=4096, wg_per_cu=8),
          dict(block=512, vec_bytes=16, unroll=4, split=1 << 15, wg_per_cu=2)]
 

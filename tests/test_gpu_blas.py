@@ -188,13 +188,15 @@ def test_workspace_zero_after_calls_and_poisoned_slots(gpu_device):
     banner("workspace reset")
     r = o_asum(x)
     xd = x.to(DEV)
-    L.asum(xd)
-    sync()
-    assert int(ws[:256].count_nonzero().item()) == 0
-    ws[256:].fill_(0xFF)                       # NaN / garbage in every partial slot
-    g = L.asum(xd).item()
-    assert rel(g, r) <= TOL
-    assert int(ws[:256].count_nonzero().item()) == 0
+    hdr = L.lift_workspace_bytes() - 16 * L.lift_max_workgroups()   # counters precede the slots
+    for k in (None, L.knobs(block=64, vec_bytes=16, unroll=1, split=256)):   # 1 and many arrival groups
+        L.asum(xd, knobs=k)
+        sync()
+        assert int(ws[:hdr].count_nonzero().item()) == 0
+        ws[hdr:].fill_(0xFF)                   # NaN / garbage in every partial slot
+        g = L.asum(xd, knobs=k).item()
+        assert rel(g, r) <= TOL
+        assert int(ws[:hdr].count_nonzero().item()) == 0
 
 
 def test_result_f64_and_raw_entry_point(gpu_device):
