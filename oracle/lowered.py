@@ -1,0 +1,160 @@
+"""Low-level asum expressions for a launch configuration (TEST INFRASTRUCTURE).
+
+The paper lowers ``asum = reduce(+,0) . map(abs)`` to device-specific
+expressions built from its OpenCL patterns (Fig. 9, Section 6.2), choosing
+split factors and vector widths per device.  This module builds the same kind
+of expression for one launch of the GPU library's asum -- from the launch
+rules its interface documents (split rounded up to whole steps of
+block * unroll vectors, one work-group per chunk, a scalar head before the
+first aligned vector and a scalar tail after the last) and the reduction tree
+its kernels use -- and evaluates it with the patterns of ``patterns.py``:
+
+    reduce-seq o join o map-workgroup(
+        toGlobal(...)
+      o reduce-seq(plus)                       (wave totals, in wave order)
+      o map-wave(iterate-6(join o map(reduce-seq(plus, 0)) o split-2))
+      o split-64
+      o map-local(iterate-log2(E)(join o map(reduce-seq(plus, 0)) o split-2)
+                  o asScalar o reduce-seq(vect-E(absAndPlus), vect-E(0)))
+      o split-(C/B) o reorder-stride^B
+    ) o split-C o asVector-E                    (C vectors per work-group)
+
+followed, when there is more than one work-group, by the same lane / wave /
+work-group tree over the work-group partials (lane t folds partials t, t+B,
+...).  The head and tail scalars are added to component 0 of lanes of the
+first and last work-group.
+
+``evaluate(x, shape, add)`` runs the expression with a caller-given binary
+``add``: with exact integer arithmetic it must equal asum (every knob point
+is a valid derivation), and with IEEE binary32 addition it predicts the
+library's floating-point result bit for bit.  Shares no code with the GPU
+library.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+from . import patterns as P
+
+
+@dataclass(frozen=True)
+class Shape:
+    """How one asum launch cuts n elements (all sizes in elements / vectors)."""
+
+    n: int
+    head: int        # scalars before the first aligned vector
+    e: int           # elements per vector load (asVector width)
+    nvec: int        # whole vectors after the head
+    block: int       # work-group size B
+    chunk: int       # vectors per work-group C (a multiple of B * unroll)
+    grid: int        # work-groups G
+
+    @property
+    def tail(self) -> int:
+        return self.n - self.head - self.nvec * self.e
+
+
+def launch_shape(n: int, elem_bytes: int, vec_bytes: int, block: int, unroll: int, split: int,
+                 misalign_elems: int = 0, max_workgroups: int = 8192) -> Shape:
+    """The documented launch rules for an explicit split (elements per chunk).
+
+    ``misalign_elems``: how many elements past a vec_bytes boundary x starts.
+    """
+    e = vec_bytes // elem_bytes
+    head = 0 if misalign_elems % e == 0 else e - misalign_elems % e
+    head = min(head, n)
+    nvec = (n - head) // e
+    step = block * unroll
+    chunk = max(1, -(-split // e))
+    chunk = max(step, -(-chunk // step) * step)
+    if -(-nvec // chunk) > max_workgroups:
+        chunk = -(-(-(-nvec // max_workgroups)) // step) * step
+    grid = max(1, -(-nvec // chunk))
+    return Shape(n, head, e, nvec, block, chunk, grid)
+
+
+def _pairwise(values, add):
+    """iterate-log2(k)(join o map(reduce-seq(plus, 0)) o split-2) on a power-of-two list.
+
+    Each level folds adjacent pairs; reduce-seq(plus, 0) of a pair is
+    plus(plus(0, a), b), written here as add(a, b) because 0 + a == a.
+    """
+    k = len(values)
+    if k & (k - 1):
+        raise ValueError("pairwise tree needs a power-of-two length")
+    level = list(values)
+    while len(level) > 1:
+        level = [add(a, b) for a, b in P.split(2)(level)]
+    return level[0]
+
+
+def _block_tree(lane_values, add):
+    """Wave butterflies (iterate-6 over 64 lanes) then a fold of the wave totals."""
+    waves = P.split(64)(lane_values)
+    totals = [_pairwise(w, add) for w in waves]
+    acc = totals[0]
+    for t in totals[1:]:
+        acc = add(acc, t)
+    return acc
+
+
+def evaluate(x, shape: Shape, add, absval, zero):
+    """The low-level expression of one asum launch on the list x.
+
+    add(a, b), absval(a) and zero define the arithmetic (exact integers, or
+    binary32).  Returns the single result.
+    """
+    s = shape
+    if len(x) != s.n:
+        raise ValueError("input length differs from the launch shape")
+    B, C, E, G = s.block, s.chunk, s.e, s.grid
+    head, tail0 = x[: s.head], x[s.head + s.nvec * E:]
+    vec_part = list(x[s.head: s.head + s.nvec * E])
+    # ragged last chunk: pad with zero vectors (neutral in the sum; reading 1)
+    vectors = P.as_vector(E)(vec_part) if vec_part else []
+    vectors += [P.Vec((zero,) * E)] * (G * C - len(vectors))
+    abs_and_plus = lambda acc, a: add(acc, absval(a))
+    lane_fold = P.reduce_seq(P.vect(E, abs_and_plus), P.Vec((zero,) * E))
+
+    partials = []
+    for b, chunk in enumerate(P.split(C)(vectors)):                 # map-workgroup
+        lanes = P.split(C // B)(P.reorder_stride(B)(chunk))         # lane t: t, t+B, ...
+        lane_acc = [list(lane_fold(v)[0]) for v in lanes]           # map-local(reduce-seq)
+        if b == 0:
+            for t, h in enumerate(head):                            # scalar head
+                lane_acc[t][0] = add(lane_acc[t][0], absval(h))
+        if b == G - 1:
+            for t, v in enumerate(tail0):                           # scalar tail
+                lane_acc[t][0] = add(lane_acc[t][0], absval(v))
+        lane_vals = [_pairwise(acc, add) for acc in lane_acc]      # iterate-log2(E)
+        partials.append(_block_tree(lane_vals, add))                # toLocal tree
+    if G == 1:
+        return partials[0]
+    # final reduce-seq o join over the work-group partials, by one work-group:
+    # lane t folds partials t, t+B, ... (from 0), then the same tree
+    padded = partials + [zero] * (-(-G // B) * B - G)
+    lane_vals = []
+    for row in P.split(len(padded) // B)(P.reorder_stride(B)(padded)):
+        acc = zero
+        for p in row:
+            acc = add(acc, p)
+        lane_vals.append(acc)
+    return _block_tree(lane_vals, add)
+
+
+def render(shape: Shape) -> str:
+    """The expression in the paper's notation (cf. Fig. 9)."""
+    s = shape
+    lanes_per_chunk = s.chunk // s.block
+    waves = s.block // 64
+    e_log = int(math.log2(s.e))
+    wg = (f"join o toGlobal(map-local(map-seq(id))) o split-1\n"
+          f"      o reduce-seq(plus, 0) o map-wave(iterate-6(join o map-local(reduce-seq(plus, 0)) o split-2))"
+          f" o split-64\n"
+          f"      o join o toLocal(map-local(iterate-{e_log}(join o map(reduce-seq(plus, 0)) o split-2)"
+          f" o asScalar o reduce-seq(vect-{s.e}(absAndPlus), vect-{s.e}(0))))\n"
+          f"      o split-{lanes_per_chunk} o reorder-stride-{s.block}")
+    text = (f"reduce-seq o join o map-workgroup(\n      {wg}\n    ) o split-{s.chunk} o asVector-{s.e}"
+            f"   [{s.grid} work-groups x {waves} waves; head {s.head}, tail {s.tail} scalars]")
+    return text

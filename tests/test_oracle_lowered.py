@@ -1,0 +1,89 @@
+"""The low-level expression of every asum launch configuration the tuner can
+choose is a valid derivation of asum (Section 6.2's device-specific lowering,
+generalised to the library's knobs): on integer inputs it equals the plain
+sum exactly, for every knob point, size and misalignment."""
+import random
+
+import pytest
+
+from oracle import lowered as LW
+from oracle import patterns as P
+from paper_1502_02389_amd import tune
+
+
+def ints(n, seed):
+    r = random.Random(seed)
+    return [r.randint(-9, 9) for _ in range(n)]
+
+
+EXACT = dict(add=lambda a, b: a + b, absval=abs, zero=0)
+
+
+def knob_points(storage):
+    seen = set()
+    for kn in tune.grid("asum", storage):
+        key = (kn["block"], kn["vec_bytes"], kn["unroll"], kn["split"] or 1 << 15)
+        if key not in seen:
+            seen.add(key)
+            yield key
+
+
+@pytest.mark.parametrize("storage,eb", [("f32", 4), ("bf16", 2)])
+def test_every_tuner_knob_point_is_a_valid_derivation(storage, eb):
+    r = random.Random(1)
+    for block, vb, unroll, split in knob_points(storage):
+        n = r.choice([0, 1, 5, 1000, 4099, 50_000])
+        mis = r.randrange(vb // eb)
+        s = LW.launch_shape(n, eb, vb, block, unroll, split, misalign_elems=mis)
+        x = ints(n, block + vb + unroll + n)
+        assert LW.evaluate(x, s, **EXACT) == sum(abs(v) for v in x), (block, vb, unroll, split, n, mis)
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 63, 64, 65, 4095, 70_001])
+@pytest.mark.parametrize("mis", [0, 1, 3])
+def test_shape_invariants(n, mis):
+    for block, vb, unroll, split in [(64, 16, 1, 256), (256, 16, 8, 1 << 15), (1024, 8, 4, 1 << 17)]:
+        s = LW.launch_shape(n, 4, vb, block, unroll, split, misalign_elems=mis)
+        assert s.chunk % (block * unroll) == 0
+        assert s.grid >= 1 and (s.grid - 1) * s.chunk < max(s.nvec, 1) <= s.grid * s.chunk or s.nvec == 0
+        assert s.head + s.nvec * s.e + s.tail == n and 0 <= s.tail < s.e and s.head < s.e
+        assert s.grid <= 8192
+
+
+def test_grid_cap_raises_chunk():
+    s = LW.launch_shape(64 * 4 * 9000, 4, 16, 64, 1, 256)
+    assert s.grid <= 8192 and s.chunk > 64
+
+
+def test_fig9b_parameters_give_the_fig9b_partition():
+    # Fig. 9b: asVector-4 o split-2048, 256 lanes x 2 float4 per work-group
+    s = LW.launch_shape(2048 * 6, 4, 16, 256, 2, 2048)
+    assert s.chunk == 512 and s.grid == 6 and s.chunk // s.block == 2
+    x = ints(2048 * 6, 7)
+    assert LW.evaluate(x, s, **EXACT) == P.asum_lowlevel_gpu_vector(2048, 2, 4)(x)[0]
+
+
+def test_render_names_the_patterns():
+    text = LW.render(LW.launch_shape(1 << 20, 4, 16, 256, 8, 1 << 15))
+    for piece in ("map-workgroup", "reorder-stride-256", "asVector-4", "iterate-6", "split-64", "toLocal",
+                  "toGlobal", "vect-4(absAndPlus)", "split-8192"):
+        assert piece in text, piece
+
+
+def test_binary32_evaluation_distinguishes_trees():
+    # a different work-group size is a different tree: same value to 1e-5,
+    # but the binary32 bits differ on random data, so a bit-exact comparison
+    # with the GPU pins the association, not just the sum
+    import numpy as np
+
+    f32 = dict(add=lambda a, b: np.float32(a) + np.float32(b), absval=lambda a: np.float32(abs(a)),
+               zero=np.float32(0))
+    differ = 0
+    for seed in range(6):
+        r = np.random.default_rng(seed)
+        x = [np.float32(v) for v in r.uniform(-1, 1, 30_000).astype(np.float32)]
+        a = LW.evaluate(x, LW.launch_shape(len(x), 4, 16, 64, 1, 256), **f32)
+        b = LW.evaluate(x, LW.launch_shape(len(x), 4, 16, 128, 1, 512), **f32)
+        assert abs(float(a) - float(b)) <= 1e-5 * float(a)
+        differ += a != b
+    assert differ >= 1
