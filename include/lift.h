@@ -112,7 +112,10 @@ typedef struct lift_knobs {
     int32_t wg_per_cu;     /* grid size in work-groups per compute unit when
                               split is 0 (per-call forms), and the size of
                               the persistent grid (batched form) */
-    int32_t reserved;      /* must be 0 */
+    int32_t row_split;     /* gemv only: 1 = each wavefront owns rows_per_wave
+                              rows; 2 = all threads of a work-group split each
+                              row (then rows_per_wave is 1 or 2 and unroll 2,
+                              4 or 8); 0 = library choice */
 } lift_knobs;
 
 /* ---- plain FP32 forms (Fig. 5) --------------------------------------- */

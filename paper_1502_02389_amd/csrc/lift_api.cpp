@@ -107,6 +107,7 @@ struct Knobs {
     int block, vec_bytes, unroll, rows;
     int64_t split;
     int wg_per_cu;
+    int row_split;  // 1: wavefront per row group, 2: work-group per row
 };
 
 // Checks the caller's knobs (0 = default) and merges them with defaults.
@@ -139,20 +140,22 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
         return LIFT_EINVAL;
     if (k->split)
         out->split = k->split;
-    if (k->wg_per_cu < 0 || k->wg_per_cu > 64 || k->reserved != 0)
+    if (k->wg_per_cu < 0 || k->wg_per_cu > 64 || k->row_split < 0 || k->row_split > 2)
         return LIFT_EINVAL;
     if (k->wg_per_cu)
         out->wg_per_cu = k->wg_per_cu;
+    if (k->row_split)
+        out->row_split = k->row_split;
     return LIFT_OK;
 }
 
 // Defaults, from the knob search on MI355X (256 CUs): reductions run about
 // one long-lived work-group per CU (fewer partials, shorter combine tail),
 // scal many one-step work-groups, gemv small work-groups of row wavefronts.
-constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0, 32};
-constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1};
-constexpr Knobs DEF_GEMV = {128, 16, 4, 1, 0, 0};
-constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2};
+constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0, 32, 1};
+constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1, 1};
+constexpr Knobs DEF_GEMV = {128, 16, 4, 1, 0, 0, 1};
+constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1};
 
 // Split a range of n elements of `ebytes` bytes at base address p into a
 // scalar head (up to the first vb-aligned address), whole vb-byte vectors,
@@ -214,6 +217,16 @@ const void *gemv_table(int dt, int acc, int vb, int rows, int unroll)
     case LIFT_F32: return gemv_kernel_f32(acc, vb, rows, unroll);
     case LIFT_BF16: return gemv_kernel_bf16(acc, vb, rows, unroll);
     case LIFT_F16: return gemv_kernel_f16(acc, vb, rows, unroll);
+    default: return nullptr;
+    }
+}
+
+const void *gemv_split_table(int dt, int acc, int vb, int rows, int unroll)
+{
+    switch (dt) {
+    case LIFT_F32: return gemv_split_kernel_f32(acc, vb, rows, unroll);
+    case LIFT_BF16: return gemv_split_kernel_bf16(acc, vb, rows, unroll);
+    case LIFT_F16: return gemv_split_kernel_f16(acc, vb, rows, unroll);
     default: return nullptr;
     }
 }
@@ -320,17 +333,33 @@ lift_status gemv_common(int64_t m, int64_t n, float alpha, int at, const void *A
         vb = eb;
         e = 1;
     }
-    const void *kern = gemv_table(at, acc, vb, k.rows, std::min(k.unroll, 4));
-    if (!kern)
-        return LIFT_EUNSUPPORTED;
     int cus = 0;
-    st = cu_count(&cus);
-    if (st != LIFT_OK)
-        return st;
-    const int64_t waves = (m + k.rows - 1) / k.rows;
-    const int64_t wpb = k.block / 64;
-    int64_t grid = (waves + wpb - 1) / wpb;
-    grid = std::min<int64_t>(grid, (int64_t)cus * 64);
+    const void *kern;
+    int64_t grid;
+    if (k.row_split == 2) {
+        // the work-group streams whole rows: 16-byte loads or element loads
+        if (vb != eb && vb != 16) {
+            vb = eb;
+            e = 1;
+        }
+        kern = gemv_split_table(at, acc, vb, k.rows, k.unroll);
+        if (!kern)
+            return LIFT_EUNSUPPORTED;
+        st = cu_count(&cus);
+        if (st != LIFT_OK)
+            return st;
+        grid = std::min<int64_t>((m + k.rows - 1) / k.rows, (int64_t)cus * 16);
+    } else {
+        kern = gemv_table(at, acc, vb, k.rows, k.unroll);
+        if (!kern)
+            return LIFT_EUNSUPPORTED;
+        st = cu_count(&cus);
+        if (st != LIFT_OK)
+            return st;
+        const int64_t waves = (m + k.rows - 1) / k.rows;
+        const int64_t wpb = k.block / 64;
+        grid = std::min<int64_t>((waves + wpb - 1) / wpb, (int64_t)cus * 64);
+    }
 
     GemvArgs a;
     a.A = A;
@@ -415,6 +444,8 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
         return LIFT_EUNSUPPORTED;  // the batched kernels load at least a dword per lane
     if (k.block > 512)
         return LIFT_EUNSUPPORTED;  // built for at most 512 threads (no register spills at 8 loads in flight)
+    if (k.row_split == 2)
+        return LIFT_EUNSUPPORTED;  // batch gemv tiles use one wavefront per row
     const int vb = k.vec_bytes;
     const int64_t e = vb / eb;
 

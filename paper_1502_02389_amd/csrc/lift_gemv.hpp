@@ -13,6 +13,9 @@
 
 #include "lift_device.hpp"
 #include "lift_internal.hpp"
+#include "lift_reduce.hpp"
+
+#include <type_traits>
 
 namespace lift {
 
@@ -213,6 +216,114 @@ __device__ __forceinline__ void gemv_row_group(const void *A, const float *x, fl
     }
 }
 
+// Row-split form: one work-group computes R rows at a time, its B threads
+// reading each row like the dot kernel reads a vector (thread t takes vectors
+// t, t+B, ...: the whole work-group streams one contiguous row), then a
+// work-group reduction per row.  This is map-workgroup over the rows with
+// the row's dot lowered to map-local + the in-work-group tree, and it keeps
+// HBM accesses as contiguous as a flat stream.
+template <class T, int ACC, int VB, int R, int U>
+__global__ void __launch_bounds__(1024) gemv_split_kernel(GemvArgs a)
+{
+    constexpr int E = Elems<T, VB>::value;
+    using V = typename Vec<VB>::type;
+    // LDS staging of the work-group reduction: binary64 for the binary64
+    // combine, the lane type otherwise (16 waves at most).
+    using LT = std::conditional_t<ACC == ACC_F64, double, typename BlockT<ACC>::type>;
+    __shared__ LT lds[R][16];
+    const int t = threadIdx.x;
+    const int64_t B = blockDim.x;
+    const int64_t row_bytes = a.lda * T::bytes;
+    const int64_t tail0 = a.nvec * E;
+    const int64_t step = B * U;
+
+    for (int64_t r0 = (int64_t)blockIdx.x * R; r0 < a.m; r0 += (int64_t)gridDim.x * R) {  // uniform
+        const char *rows[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            rows[r] = reinterpret_cast<const char *>(a.A) + min(r0 + r, a.m - 1) * row_bytes;
+        RowAcc<ACC, E> acc[R];
+        int64_t base = 0;
+        for (; base + step <= a.nvec; base += step) {
+            float xf[U][E];
+            V va[R][U];
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                load_x<E>(a.x, base + t + k * B, xf[k]);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    va[r][k] = load_stream<VB>(rows[r], base + t + k * B);
+            loads_in_flight();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    float af[E];
+                    decode<T, VB>(va[r][k], af);
+                    acc[r].add(af, xf[k]);
+                }
+        }
+        if (base < a.nvec) {  // final partial step, clamped loads, zeros past the end
+            float xf[U][E];
+            V va[R][U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int64_t v = min(base + t + k * B, a.nvec - 1);
+                load_x<E>(a.x, v, xf[k]);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    va[r][k] = load_stream<VB>(rows[r], v);
+            }
+            loads_in_flight();
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const bool in = base + t + k * B < a.nvec;
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    xf[k][e] = in ? xf[k][e] : 0.f;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const bool in = base + t + k * B < a.nvec;
+                    float af[E];
+                    decode<T, VB>(va[r][k], af);
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+                        af[e] = in ? af[e] : 0.f;
+                    acc[r].add(af, xf[k]);
+                }
+        }
+        if (tail0 + t < a.n) {  // fewer than E trailing columns
+            const float xs = a.x[tail0 + t];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                acc[r].add_scalar(load_elem<T>(rows[r], tail0 + t), xs);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (ACC == ACC_F64) {
+                double d = block_sum<double>((double)acc[r].value(), lds[r]);
+                if (t == 0 && r0 + r < a.m) {
+                    double by = a.beta == 0.f ? 0.0 : (double)a.beta * (double)a.y[r0 + r];
+                    a.y[r0 + r] = (float)((double)a.alpha * d + by);
+                }
+            } else if constexpr (ACC == ACC_COMP) {
+                Pair p = block_sum<Pair>(acc[r].value(), lds[r]);
+                if (t == 0 && r0 + r < a.m)
+                    store_row<ACC>(a.y, r0 + r, a.alpha, a.beta, p.s + p.c);
+            } else {
+                float d = block_sum<float>(acc[r].value(), lds[r]);
+                if (t == 0 && r0 + r < a.m)
+                    store_row<ACC>(a.y, r0 + r, a.alpha, a.beta, d);
+            }
+        }
+    }
+}
+
 template <class T, int ACC, int VB, int R, int U>
 __global__ void __launch_bounds__(1024) gemv_kernel(GemvArgs a)
 {
@@ -231,6 +342,44 @@ const void *gemv_pick_unroll(int unroll)
     case 1: return reinterpret_cast<const void *>(&gemv_kernel<T, ACC, VB, R, 1>);
     case 2: return reinterpret_cast<const void *>(&gemv_kernel<T, ACC, VB, R, 2>);
     case 4: return reinterpret_cast<const void *>(&gemv_kernel<T, ACC, VB, R, 4>);
+    case 8: return reinterpret_cast<const void *>(&gemv_kernel<T, ACC, VB, R, 8>);
+    default: return nullptr;
+    }
+}
+
+template <class T, int ACC, int VB, int R>
+const void *gemv_split_pick_unroll(int unroll)
+{
+    switch (unroll) {
+    case 2: return reinterpret_cast<const void *>(&gemv_split_kernel<T, ACC, VB, R, 2>);
+    case 4: return reinterpret_cast<const void *>(&gemv_split_kernel<T, ACC, VB, R, 4>);
+    case 8: return reinterpret_cast<const void *>(&gemv_split_kernel<T, ACC, VB, R, 8>);
+    default: return nullptr;
+    }
+}
+
+// Row-split instances: element loads (unaligned rows) or 16-byte loads,
+// 1 or 2 rows per iteration.
+template <class T, int ACC>
+const void *gemv_split_pick(int vec_bytes, int rows, int unroll)
+{
+    if (rows != 1 && rows != 2)
+        return nullptr;
+    if (vec_bytes == T::bytes)
+        return rows == 1 ? gemv_split_pick_unroll<T, ACC, T::bytes, 1>(unroll)
+                         : gemv_split_pick_unroll<T, ACC, T::bytes, 2>(unroll);
+    if (vec_bytes == 16)
+        return rows == 1 ? gemv_split_pick_unroll<T, ACC, 16, 1>(unroll) : gemv_split_pick_unroll<T, ACC, 16, 2>(unroll);
+    return nullptr;
+}
+
+template <class T>
+const void *pick_gemv_split(int acc, int vec_bytes, int rows, int unroll)
+{
+    switch (acc) {
+    case ACC_F32: return gemv_split_pick<T, ACC_F32>(vec_bytes, rows, unroll);
+    case ACC_COMP: return gemv_split_pick<T, ACC_COMP>(vec_bytes, rows, unroll);
+    case ACC_F64: return gemv_split_pick<T, ACC_F64>(vec_bytes, rows, unroll);
     default: return nullptr;
     }
 }

@@ -8,4 +8,9 @@ const void *gemv_kernel_f16(int acc, int vec_bytes, int rows, int unroll)
     return pick_gemv<F16>(acc, vec_bytes, rows, unroll);
 }
 
+const void *gemv_split_kernel_f16(int acc, int vec_bytes, int rows, int unroll)
+{
+    return pick_gemv_split<F16>(acc, vec_bytes, rows, unroll);
+}
+
 }  // namespace lift

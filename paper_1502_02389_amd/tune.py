@@ -104,8 +104,11 @@ def grid(op: str, storage: str, quick: bool = False):
     if op == "gemv":
         blocks = (64, 256, 1024) if quick else (64, 128, 256, 512, 1024)
         vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)
-        for b, v, u, r in itertools.product(blocks, vecs, (1, 2, 4), (1, 2, 4)):
-            yield dict(block=b, vec_bytes=v, unroll=u, rows_per_wave=r)
+        for b, v, u, r in itertools.product(blocks, vecs, (1, 2, 4, 8), (1, 2, 4)):
+            yield dict(block=b, vec_bytes=v, unroll=u, rows_per_wave=r, row_split=1)
+        # a work-group per row (16-byte loads)
+        for b, u, r in itertools.product((128, 256, 512, 1024), (2, 4, 8), (1, 2)):
+            yield dict(block=b, vec_bytes=16, unroll=u, rows_per_wave=r, row_split=2)
         return
     blocks = (256, 512) if quick else (128, 256, 512, 1024)
     vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)

@@ -62,7 +62,7 @@ def test_enum_values_match_header():
 
 
 def test_struct_layouts():
-    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, int32 reserved
+    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, int32 row_split
     assert ctypes.sizeof(B.lift_knobs) == 32
     assert B.lift_knobs.split.offset == 16 and B.lift_knobs.wg_per_cu.offset == 24
     # lift_problem: int32 kind, int32 reserved, int64 m, n, lda, 3 pointers, 2 floats
@@ -139,10 +139,11 @@ def test_ex_rejects_bad_enums_and_knobs():
     assert L.lift_asum_ex(8, L.LIFT_BF16, X + 1, 0, 0, R, WS, w) == L.LIFT_EINVAL  # bf16 misaligned
     for bad in (B.knobs(block=96), B.knobs(block=2048), B.knobs(block=32), B.knobs(vec_bytes=3),
                 B.knobs(vec_bytes=2), B.knobs(vec_bytes=32), B.knobs(unroll=3), B.knobs(unroll=16),
-                B.knobs(rows_per_wave=8), B.knobs(split=-1)):
+                B.knobs(rows_per_wave=8), B.knobs(split=-1), B.knobs(row_split=3), B.knobs(row_split=-1)):
         assert L.lift_asum_ex(8, 0, X, 0, 0, R, WS, w, bad) == L.LIFT_EINVAL
     assert L.lift_gemv_ex(4, 8, 1.0, 5, X, 8, Y, 0.5, R, 0) == L.LIFT_EINVAL
     assert L.lift_gemv_ex(4, 8, 1.0, 0, X, 8, Y, 0.5, R, 4) == L.LIFT_EINVAL
+    assert L.lift_gemv_ex(4, 8, 1.0, 0, X, 8, Y, 0.5, R, 0, B.knobs(row_split=5)) == L.LIFT_EINVAL
     assert L.lift_scal_ex(8, 1.0, X, Y, B.knobs(unroll=5)) == L.LIFT_EINVAL
 
 
@@ -205,9 +206,8 @@ def test_batch_rejects_bad_problems():
     assert _batch_status([ok_red], knobs=B.knobs(vec_bytes=2), storage=L.LIFT_BF16) == L.LIFT_EUNSUPPORTED
     assert _batch_status([ok_red], count=-1) == L.LIFT_EINVAL
     assert _batch_status([ok_red], knobs=B.knobs(block=1024)) == L.LIFT_EUNSUPPORTED
-    k = B.knobs()
-    k.reserved = 3
-    assert _batch_status([ok_red], knobs=k) == L.LIFT_EINVAL
+    assert _batch_status([ok_red], knobs=B.knobs(row_split=3)) == L.LIFT_EINVAL
+    assert _batch_status([ok_red], knobs=B.knobs(row_split=2)) == L.LIFT_EUNSUPPORTED
 
 
 @cpu_only

@@ -297,14 +297,36 @@ def test_gemv_integer_bitexact_nonsquare_lda(gpu_device):
     y = W.integers(m, -8, 8, g0)
     banner("gemv integers", m, n, lda)
     r, _ = o_gemv(1.0, A, x, 0.5, y)
+    Ad, xd = A.to(DEV), x.to(DEV)
     for rows in (1, 2, 4):
         for v in (4, 8, 16):
-            for u in (1, 2, 4):
+            for u in (1, 2, 4, 8):
                 for b in (64, 256, 1024):
                     yd = y.to(DEV)
-                    L.gemv(1.0, A.to(DEV), x.to(DEV), 0.5, yd, lda=lda,
-                           knobs=L.knobs(block=b, vec_bytes=v, unroll=u, rows_per_wave=rows))
+                    L.gemv(1.0, Ad, xd, 0.5, yd, lda=lda,
+                           knobs=L.knobs(block=b, vec_bytes=v, unroll=u, rows_per_wave=rows, row_split=1))
                     assert np.array_equal(yd.cpu().numpy().astype(np.float64), r), (rows, v, u, b)
+    # work-group-per-row form
+    for rows in (1, 2):
+        for v in (4, 16):
+            for u in (2, 4, 8):
+                for b in (64, 256, 1024):
+                    yd = y.to(DEV)
+                    L.gemv(1.0, Ad, xd, 0.5, yd, lda=lda,
+                           knobs=L.knobs(block=b, vec_bytes=v, unroll=u, rows_per_wave=rows, row_split=2))
+                    assert np.array_equal(yd.cpu().numpy().astype(np.float64), r), ("split", rows, v, u, b)
+
+
+@pytest.mark.parametrize("size", W.CONFIG3_SIZES)
+def test_gemv_config3_row_split(gpu_device, size):
+    A, x, y, alpha, beta = W.config3(size)
+    banner("gemv config3 row split", size)
+    Ad, xd = A.to(DEV), x.to(DEV)
+    for rows, u in ((1, 8), (2, 4)):
+        yd = y.to(DEV)
+        L.gemv(alpha, Ad, xd, beta, yd, knobs=L.knobs(block=256, vec_bytes=16, unroll=u, rows_per_wave=rows,
+                                                     row_split=2))
+        _gemv_check(alpha, A, x, beta, y, yd)
 
 
 @pytest.mark.parametrize("m,n,lda", [(1, 1, 1), (3, 5, 5), (7, 64, 64), (65, 257, 259), (130, 4099, 4100),

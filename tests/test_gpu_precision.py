@@ -120,7 +120,16 @@ def test_gemv_16bit_shapes_and_widths(gpu_device, storage, acc):
         for rows in (1, 4):
             banner("gemv 16-bit", storage, acc, v, rows)
             yd = y.to(DEV)
-            L.gemv(0.75, Ad, xd, 0.5, yd, acc=acc, lda=lda, knobs=L.knobs(vec_bytes=v, rows_per_wave=rows))
+            L.gemv(0.75, Ad, xd, 0.5, yd, acc=acc, lda=lda, knobs=L.knobs(vec_bytes=v, rows_per_wave=rows,
+                                                                         row_split=1))
+            err = np.abs(yd.cpu().numpy().astype(np.float64) - r) / mass
+            assert float(err.max()) <= BOUND[acc]
+    for v in (2, 16):
+        for rows in (1, 2):
+            banner("gemv 16-bit row split", storage, acc, v, rows)
+            yd = y.to(DEV)
+            L.gemv(0.75, Ad, xd, 0.5, yd, acc=acc, lda=lda,
+                   knobs=L.knobs(block=256, vec_bytes=v, unroll=4, rows_per_wave=rows, row_split=2))
             err = np.abs(yd.cpu().numpy().astype(np.float64) - r) / mass
             assert float(err.max()) <= BOUND[acc]
 
