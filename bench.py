@@ -17,10 +17,11 @@ Also reported on the same JSON line:
                  region; peak 8 TB/s; HBM traffic per launch from rocprofv3
                  counters when they were taken on the current kernel source
                  (else null)
-  cpu_baseline : the binary64 oracle (single thread) on a bounded sample of the
-                 same workload, same data
+  cpu_baseline : the binary64 oracle on the same workload and data, in its
+                 split-join form on the host cores (value) and sequentially on
+                 one thread; each timed for a bounded number of seconds
   kernels      : per-kernel average durations from back-to-back launches
-  forms        : gemv fp32 (4096^2, 8192^2), 16-bit storage (n = 2^26 asum/dot,
+  forms        : gemv fp32 (4096^2, 8192^2, 16384^2), 16-bit storage (n = 2^26 asum/dot,
                  bf16 gemv 16384^2) in each accumulation variant, as GB/s and
                  binary32-equivalent GB/s
 
@@ -236,29 +237,45 @@ def main():
 
 
 def cpu_baseline(x_cpu, y_cpu, alpha, seconds, gpu_set, step_bytes):
-    """The binary64 oracle, single thread, timed on whole steps of the same
-    workload until `seconds` have elapsed (at least one step)."""
+    """The binary64 oracle timed on whole steps of the same workload (scal,
+    asum, dot over the same host arrays): first the sequential composition on
+    one thread, then its split-join form (rule 3d) on every host core this
+    process may use, each until `seconds` have elapsed (at least one step)."""
     import oracle
 
     xs, ys = x_cpu.numpy(), y_cpu.numpy()
     oracle.asum(xs[:1024])  # load
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
+    threads = oracle.host_threads()
+
+    def timed(step):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            res = step()
+            reps += 1
+            if time.perf_counter() - t0 >= seconds:
+                return reps, time.perf_counter() - t0, res
+
+    def seq():
         oracle.scal(alpha, xs)
-        ra = oracle.asum(xs)
-        rd = oracle.dot(xs, ys)
-        reps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    el = time.perf_counter() - t0
-    gbs = step_bytes * reps / el / 1e9
+        return oracle.asum(xs), oracle.dot(xs, ys)
+
+    def par():
+        oracle.scal_par(alpha, xs, threads)
+        return oracle.asum_par(xs, threads), oracle.dot_par(xs, ys, threads)
+
+    r1, el1, (ra, rd) = timed(seq)
+    rp, elp, _ = timed(par)
+    g1 = step_bytes * r1 / el1 / 1e9
+    gp = step_bytes * rp / elp / 1e9
     ga, gd = float(gpu_set["ra"].item()), float(gpu_set["rd"].item())
     mass = oracle.dot_absmass(xs, ys)
-    log("cpu oracle", reps, "steps in", f"{el:.1f}s", f"{gbs:.3f} GB/s")
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full steps (scal+asum+dot, n=2^24) of the binary64 C oracle, one thread, "
-                      f"{el:.1f} s",
+    log("cpu oracle 1 thread:", r1, "steps in", f"{el1:.1f}s", f"{g1:.3f} GB/s;",
+        threads, "threads:", rp, "steps in", f"{elp:.1f}s", f"{gp:.3f} GB/s")
+    return {"value": round(gp, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rp} full steps (scal+asum+dot, n=2^24, same arrays) of the binary64 C oracle in its "
+                      f"split-join form on {threads} threads, {elp:.1f} s",
+            "single_thread": {"value": round(g1, 4), "unit": "GB/s", "cores": 1,
+                              "sample": f"{r1} full steps of the sequential composition, {el1:.1f} s"},
             "gpu_vs_oracle": {"asum_rel_err": abs(ga - ra) / ra, "dot_err_over_absmass": abs(gd - rd) / mass}}
 
 
@@ -293,8 +310,8 @@ def forms(L, W, dev, stream):
                      "fp32_equiv_GB_s": round(fp32_bytes / (us * 1e-6) / 1e9, 1)}
         log("form", name, out[name])
 
-    # gemv fp32, square 4096 and 8192
-    for size in W.CONFIG3_SIZES:
+    # gemv fp32, square 4096 and 8192, and 16384 (A 1 GiB) for the large-size roofline
+    for size in W.CONFIG3_SIZES + (16384,):
         A, x, y, alpha, beta = W.config3(size)
         nb = 4 * size * size + 4 * size + 8 * size
         ns = max(2, -(-COLD_BYTES // nb))

@@ -97,7 +97,9 @@ typedef enum lift_acc {
  * selects the library default for that field. */
 typedef struct lift_knobs {
     int32_t block;         /* work-group size: 64, 128, 256, 512 or 1024
-                              (batched form: at most 512) */
+                              (batched form: at most 512; gemv lowers it to
+                              what the instance's registers allow: with
+                              many rows x loads in flight, 512 or 256) */
     int32_t vec_bytes;     /* bytes per lane per load: 2 (16-bit storage
                               only), 4, 8 or 16 -- asVector width times the
                               element size */
@@ -110,12 +112,18 @@ typedef struct lift_knobs {
                               per tile (gemv tiles: about this many matrix
                               elements, whole rows) */
     int32_t wg_per_cu;     /* grid size in work-groups per compute unit when
-                              split is 0 (per-call forms), and the size of
+                              split is 0 (per-call forms), the grid cap of
+                              the work-group-per-row gemv, and the size of
                               the persistent grid (batched form) */
     int32_t row_split;     /* gemv only: 1 = each wavefront owns rows_per_wave
                               rows; 2 = all threads of a work-group split each
                               row (then rows_per_wave is 1 or 2 and unroll 2,
-                              4 or 8); 0 = library choice */
+                              4 or 8; when one pass of block * unroll loads
+                              covers a row, each thread keeps its part of x
+                              in registers for all its rows); 0 = library
+                              choice (2, with a work-group of up to 512
+                              threads sized to the row, where x fits in
+                              registers; else 1) */
 } lift_knobs;
 
 /* ---- plain FP32 forms (Fig. 5) --------------------------------------- */

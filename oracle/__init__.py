@@ -48,7 +48,7 @@ def build(force: bool = True) -> str:
     tmp = _LIB + ".tmp"
     cmd = [
         "gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fno-fast-math",
-        "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm",
+        "-ffp-contract=off", "-pthread", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm",
     ]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
@@ -67,8 +67,12 @@ def _configure(lib):
     gemv_args = [i64, i64, dbl, i32, vp, i64, i32, vp, dbl, i32, vp, dp]
     lib.oracle_gemv.argtypes = gemv_args
     lib.oracle_gemv_absmass.argtypes = gemv_args
+    lib.oracle_scal_par.argtypes = [i64, dbl, i32, vp, dp, i32]
+    lib.oracle_asum_par.argtypes = [i64, i32, vp, dp, i32]
+    lib.oracle_dot_par.argtypes = [i64, i32, vp, i32, vp, dp, i32]
     for name in ("oracle_widen", "oracle_scal", "oracle_asum", "oracle_dot",
-                 "oracle_dot_absmass", "oracle_gemv", "oracle_gemv_absmass"):
+                 "oracle_dot_absmass", "oracle_gemv", "oracle_gemv_absmass",
+                 "oracle_scal_par", "oracle_asum_par", "oracle_dot_par"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -195,3 +199,43 @@ def gemv_absmass(alpha: float, A: np.ndarray, x: np.ndarray, beta: float, y: np.
                  adtype=None, lda=None) -> np.ndarray:
     """|alpha| sum_j |A_ij x_j| + |beta y_i| -- gemv's per-row error denominator."""
     return _gemv(_load().oracle_gemv_absmass, alpha, A, x, beta, y, adtype, lda)
+
+
+# ---------------------------------------------------------------- split-join
+def host_threads() -> int:
+    """Threads for the split-join form: the cores this process may use,
+    capped by OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, min(n, 256))
+
+
+def scal_par(alpha: float, x: np.ndarray, threads: int, dtype=None) -> np.ndarray:
+    """scal as a map over `threads` chunks, each chunk on its own thread."""
+    x = _flat(x)
+    out = np.empty(x.size, dtype=np.float64)
+    _check(_load().oracle_scal_par(x.size, float(alpha), _code(x, dtype), _ptr(x),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(threads)), "scal_par")
+    return out
+
+
+def asum_par(x: np.ndarray, threads: int, dtype=None) -> float:
+    """reduce(add, 0) o join o map(asum) o split: chunk sums on threads, then
+    their sum in chunk order (rule 3d)."""
+    x = _flat(x)
+    r = ctypes.c_double()
+    _check(_load().oracle_asum_par(x.size, _code(x, dtype), _ptr(x), ctypes.byref(r), int(threads)), "asum_par")
+    return r.value
+
+
+def dot_par(x: np.ndarray, y: np.ndarray, threads: int, dtype=None, ydtype=None) -> float:
+    """dot in the same split-join form as asum_par."""
+    x, y = _flat(x), _flat(y)
+    if x.size != y.size:
+        raise ValueError("dot of unequal lengths")
+    r = ctypes.c_double()
+    _check(_load().oracle_dot_par(x.size, _code(x, dtype), _ptr(x), _code(y, ydtype if ydtype else dtype),
+                                  _ptr(y), ctypes.byref(r), int(threads)), "dot_par")
+    return r.value

@@ -34,6 +34,15 @@
  *     composition above;
  *   - A is row-major with leading dimension lda >= n (map over rows).
  *
+ * For timing on a multi-core host there is also the split-join form of
+ * scal, asum and dot on p threads (rule 3d of Section 4: a reduction may be
+ * split into partial reductions whose results are reduced again, valid when
+ * z is the identity of f): split the input into p chunks, run the sequential
+ * composition above on each chunk on its own thread (a map over the chunks),
+ * then reduce the p partial results in chunk order.  A shorter last chunk is
+ * the same as padding with z.  On integer-valued inputs it equals the
+ * sequential form exactly; in floating point it is another association.
+ *
  * Pins (see tests/test_oracle_blas.py): closed forms, exact integer sums,
  * math.fsum (correctly rounded) within the sequential-fold error bound,
  * Hadamard orthogonality, brute force with Python Fractions, and the
@@ -43,6 +52,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <pthread.h>
 
 enum { OR_F32 = 0, OR_BF16 = 1, OR_F16 = 2, OR_F64 = 3 };
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2 };
@@ -333,4 +343,114 @@ int oracle_gemv_absmass(int64_t m, int64_t n, double alpha, int at, const void *
                         int xt, const void *x, double beta, int yt, const void *y, double *out)
 {
     return gemv_common(m, n, alpha, at, A, lda, xt, x, beta, yt, y, fn_absmult, 1, out);
+}
+
+/* ------------------------------------------------------------------ */
+/* split-join form on p threads (rule 3d)                               */
+/* ------------------------------------------------------------------ */
+
+enum { PAR_SCAL = 0, PAR_ASUM = 1, PAR_DOT = 2 };
+enum { PAR_MAX_THREADS = 256 };
+
+typedef struct {
+    int op;
+    int64_t n;          /* this chunk's length */
+    int xt, yt;
+    const void *x, *y;  /* this chunk's first elements */
+    double alpha;
+    double *out;        /* scal: this chunk's first output */
+    double partial;     /* asum / dot: the chunk's reduction */
+    int rc;
+} par_chunk;
+
+static size_t elem_size(int dtype)
+{
+    return dtype == OR_F64 ? 8 : dtype == OR_F32 ? 4 : 2;
+}
+
+static void *par_worker(void *arg)
+{
+    par_chunk *c = arg;
+    switch (c->op) {
+    case PAR_SCAL:
+        c->rc = oracle_scal(c->n, c->alpha, c->xt, c->x, c->out);
+        break;
+    case PAR_ASUM:
+        c->rc = oracle_asum(c->n, c->xt, c->x, &c->partial);
+        break;
+    default:
+        c->rc = oracle_dot(c->n, c->xt, c->x, c->yt, c->y, &c->partial);
+        break;
+    }
+    return NULL;
+}
+
+/* map over the p chunks on p threads, then (asum, dot) reduce(add, 0) over
+   the chunk results in chunk order */
+static int split_join(int op, int64_t n, int xt, const void *x, int yt, const void *y, double alpha,
+                      double *out, double *result, int threads)
+{
+    if (n < 0 || threads < 1 || threads > PAR_MAX_THREADS || !valid_dtype(xt) ||
+        (op == PAR_DOT && !valid_dtype(yt)))
+        return OR_EINVAL;
+    if (n > 0 && (!x || (op == PAR_DOT && !y) || (op == PAR_SCAL && !out)))
+        return OR_EINVAL;
+    if (op != PAR_SCAL && !result)
+        return OR_EINVAL;
+    int64_t p = threads;
+    int64_t k = n > 0 ? (n + p - 1) / p : 0;   /* chunk length of split(k) */
+    if (k > 0)
+        p = (n + k - 1) / k;                    /* chunks actually formed */
+    else
+        p = 0;
+    par_chunk c[PAR_MAX_THREADS];
+    pthread_t tid[PAR_MAX_THREADS];
+    int started[PAR_MAX_THREADS];
+    for (int64_t i = 0; i < p; ++i) {
+        int64_t lo = i * k, len = (n - lo < k) ? n - lo : k;
+        c[i].op = op;
+        c[i].n = len;
+        c[i].xt = xt;
+        c[i].yt = yt;
+        c[i].x = (const char *)x + (size_t)lo * elem_size(xt);
+        c[i].y = op == PAR_DOT ? (const char *)y + (size_t)lo * elem_size(yt) : NULL;
+        c[i].alpha = alpha;
+        c[i].out = op == PAR_SCAL ? out + lo : NULL;
+        c[i].partial = 0.0;
+        c[i].rc = OR_OK;
+        started[i] = pthread_create(&tid[i], NULL, par_worker, &c[i]) == 0;
+        if (!started[i])
+            par_worker(&c[i]);                  /* no thread: run the chunk here */
+    }
+    int rc = OR_OK;
+    for (int64_t i = 0; i < p; ++i) {
+        if (started[i])
+            pthread_join(tid[i], NULL);
+        if (c[i].rc != OR_OK)
+            rc = c[i].rc;
+    }
+    if (rc != OR_OK)
+        return rc;
+    if (op != PAR_SCAL) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < p; ++i)
+            acc = fn_add(acc, c[i].partial, NULL);
+        *result = acc;
+    }
+    return OR_OK;
+}
+
+int oracle_scal_par(int64_t n, double alpha, int xt, const void *x, double *out, int threads)
+{
+    return split_join(PAR_SCAL, n, xt, x, OR_F64, NULL, alpha, out, NULL, threads);
+}
+
+int oracle_asum_par(int64_t n, int xt, const void *x, double *result, int threads)
+{
+    return split_join(PAR_ASUM, n, xt, x, OR_F64, NULL, 0.0, NULL, result, threads);
+}
+
+int oracle_dot_par(int64_t n, int xt, const void *x, int yt, const void *y, double *result, int threads)
+{
+    return split_join(PAR_DOT, n, xt, x, yt, y, 0.0, NULL, result, threads);
 }

@@ -59,6 +59,27 @@ lift_status cu_count(int *out)
     return LIFT_OK;
 }
 
+// The largest work-group a kernel was compiled for (its launch bound),
+// cached per kernel.
+lift_status max_block(const void *kernel, int *out)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, int>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto &kv : cache)
+        if (kv.first == kernel) {
+            *out = kv.second;
+            return LIFT_OK;
+        }
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, kernel);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    cache.emplace_back(kernel, attr.maxThreadsPerBlock);
+    *out = attr.maxThreadsPerBlock;
+    return LIFT_OK;
+}
+
 lift_status launch(const void *kernel, int64_t grid, int block, void *args, hipStream_t s)
 {
     void *argv[] = {args};
@@ -151,10 +172,11 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
 
 // Defaults, from the knob search on MI355X (256 CUs): reductions run about
 // one long-lived work-group per CU (fewer partials, shorter combine tail),
-// scal many one-step work-groups, gemv small work-groups of row wavefronts.
+// scal many one-step work-groups, gemv a work-group per row with x held in
+// registers where one step covers a row (row_split 0 = chosen per shape).
 constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0, 32, 1};
 constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1, 1};
-constexpr Knobs DEF_GEMV = {128, 16, 4, 1, 0, 0, 1};
+constexpr Knobs DEF_GEMV = {256, 16, 8, 1, 0, 0, 0};
 constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1};
 
 // Split a range of n elements of `ebytes` bytes at base address p into a
@@ -221,12 +243,12 @@ const void *gemv_table(int dt, int acc, int vb, int rows, int unroll)
     }
 }
 
-const void *gemv_split_table(int dt, int acc, int vb, int rows, int unroll)
+const void *gemv_split_table(int dt, int acc, int vb, int rows, int unroll, bool xs)
 {
     switch (dt) {
-    case LIFT_F32: return gemv_split_kernel_f32(acc, vb, rows, unroll);
-    case LIFT_BF16: return gemv_split_kernel_bf16(acc, vb, rows, unroll);
-    case LIFT_F16: return gemv_split_kernel_f16(acc, vb, rows, unroll);
+    case LIFT_F32: return gemv_split_kernel_f32(acc, vb, rows, unroll, xs);
+    case LIFT_BF16: return gemv_split_kernel_bf16(acc, vb, rows, unroll, xs);
+    case LIFT_F16: return gemv_split_kernel_f16(acc, vb, rows, unroll, xs);
     default: return nullptr;
     }
 }
@@ -323,8 +345,6 @@ lift_status gemv_common(int64_t m, int64_t n, float alpha, int at, const void *A
     if (m == 0)
         return LIFT_OK;
 
-    if (!knobs || !knobs->rows_per_wave)
-        k.rows = m * n > ((int64_t)1 << 25) ? 2 : 1;  // long matrices: share x loads over 2 rows
     // Vector path needs every row start and x aligned for the chosen width.
     int vb = k.vec_bytes;
     int64_t e = vb / eb;
@@ -333,29 +353,56 @@ lift_status gemv_common(int64_t m, int64_t n, float alpha, int at, const void *A
         vb = eb;
         e = 1;
     }
+    if (k.row_split == 0) {
+        // library choice: a work-group per row where one step of at most 512
+        // threads covers the row (x then stays in registers), sized to the row
+        // unless the caller fixed the work-group size
+        const int64_t nvec = n / e;
+        const bool fits = (vb == 16 || vb == eb) && nvec <= (int64_t)512 * k.unroll;
+        k.row_split = fits ? 2 : 1;
+        if (fits && (!knobs || !knobs->block)) {
+            k.block = 64;
+            while ((int64_t)k.block * k.unroll < nvec && k.block < 512)
+                k.block *= 2;
+        }
+    }
+    if (!knobs || !knobs->rows_per_wave)  // wavefront form on long matrices: share x loads over 2 rows
+        k.rows = k.row_split == 1 && m * n > ((int64_t)1 << 25) ? 2 : 1;
     int cus = 0;
     const void *kern;
     int64_t grid;
+    int bound = 0;
     if (k.row_split == 2) {
         // the work-group streams whole rows: 16-byte loads or element loads
         if (vb != eb && vb != 16) {
             vb = eb;
             e = 1;
         }
-        kern = gemv_split_table(at, acc, vb, k.rows, k.unroll);
+        kern = gemv_split_table(at, acc, vb, k.rows, k.unroll, false);
         if (!kern)
             return LIFT_EUNSUPPORTED;
         st = cu_count(&cus);
+        if (st == LIFT_OK)
+            st = max_block(kern, &bound);  // the x-stationary instance has the same bound
         if (st != LIFT_OK)
             return st;
-        grid = std::min<int64_t>((m + k.rows - 1) / k.rows, (int64_t)cus * 16);
+        k.block = std::min(k.block, bound);
+        // rows that one step of the work-group covers: x stays in registers
+        const bool xs = n / e <= (int64_t)k.block * k.unroll;
+        if (xs)
+            kern = gemv_split_table(at, acc, vb, k.rows, k.unroll, true);
+        const int64_t per_cu = k.wg_per_cu ? k.wg_per_cu : (xs ? 8 : 16);
+        grid = std::min<int64_t>((m + k.rows - 1) / k.rows, (int64_t)cus * per_cu);
     } else {
         kern = gemv_table(at, acc, vb, k.rows, k.unroll);
         if (!kern)
             return LIFT_EUNSUPPORTED;
         st = cu_count(&cus);
+        if (st == LIFT_OK)
+            st = max_block(kern, &bound);
         if (st != LIFT_OK)
             return st;
+        k.block = std::min(k.block, bound);
         const int64_t waves = (m + k.rows - 1) / k.rows;
         const int64_t wpb = k.block / 64;
         grid = std::min<int64_t>((waves + wpb - 1) / wpb, (int64_t)cus * 64);

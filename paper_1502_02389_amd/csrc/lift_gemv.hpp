@@ -109,6 +109,21 @@ struct RowAcc<ACC_COMP, E> {
     __device__ __forceinline__ Pair value() const { return p; }
 };
 
+// Largest work-group an instance is compiled for.  R x U vector loads and
+// U x E values of x are live at once; the register estimate below keeps
+// every instance within the budget its launch bound grants (1024 threads:
+// 128 registers per lane, 512: 256, 256: 512) so none spills.  The host
+// reads the bound back from the kernel and lowers the work-group size to it.
+template <class T, int ACC, int VB, int R, int U>
+constexpr int gemv_bound()
+{
+    constexpr int E = Elems<T, VB>::value;
+    constexpr int load_regs = R * U * (VB < 4 ? 2 : VB / 4);  // sub-dword loads: value + address
+    constexpr int acc_regs = ACC == ACC_COMP ? R * 2 + 2 * E : R * E;
+    constexpr int regs = load_regs + U * E + acc_regs;
+    return regs <= 64 ? 1024 : regs <= 200 ? 512 : 256;
+}
+
 template <int ACC>
 __device__ __forceinline__ void store_row(float *y, int64_t i, float alpha, float beta, float dotv)
 {
@@ -223,7 +238,7 @@ __device__ __forceinline__ void gemv_row_group(const void *A, const float *x, fl
 // the row's dot lowered to map-local + the in-work-group tree, and it keeps
 // HBM accesses as contiguous as a flat stream.
 template <class T, int ACC, int VB, int R, int U>
-__global__ void __launch_bounds__(1024) gemv_split_kernel(GemvArgs a)
+__global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_split_kernel(GemvArgs a)
 {
     constexpr int E = Elems<T, VB>::value;
     using V = typename Vec<VB>::type;
@@ -324,8 +339,134 @@ __global__ void __launch_bounds__(1024) gemv_split_kernel(GemvArgs a)
     }
 }
 
+// The row's finished dot (a wave's partial, then the work-group's fold of
+// the wave partials) in the LDS type of the accumulation variant.
+template <int ACC>
+using RowPartT = std::conditional_t<ACC == ACC_F64, double, typename BlockT<ACC>::type>;
+
+template <int ACC, int E>
+__device__ __forceinline__ RowPartT<ACC> wave_row_partial(const RowAcc<ACC, E> &acc)
+{
+    if constexpr (ACC == ACC_F64)
+        return wave_sum((double)acc.value());
+    else
+        return wave_sum(acc.value());
+}
+
+template <int ACC>
+__device__ __forceinline__ void store_row_part(const GemvArgs &a, int64_t i, RowPartT<ACC> d)
+{
+    if constexpr (ACC == ACC_F64) {
+        double by = a.beta == 0.f ? 0.0 : (double)a.beta * (double)a.y[i];
+        a.y[i] = (float)((double)a.alpha * d + by);
+    } else if constexpr (ACC == ACC_COMP) {
+        store_row<ACC>(a.y, i, a.alpha, a.beta, d.s + d.c);
+    } else {
+        store_row<ACC>(a.y, i, a.alpha, a.beta, d);
+    }
+}
+
+// Row-split form with x held in registers, for rows that one step of the
+// work-group covers (nvec <= B * U).  Thread t needs the same x vectors
+// t, t+B, ..., t+(U-1)B for every row, so it loads them once and each row
+// costs only its A loads; x is read once per work-group instead of once per
+// row.  Row groups are visited grid-stride (r0 = (blockIdx.x + j G) R).
+// Every wave folds its row partial with the butterfly and parks it in LDS;
+// after 16 rows one barrier lets 16 threads fold those rows' wave partials
+// in wave order and store y.  Two LDS banks alternate, so one barrier per 16
+// rows is enough (a bank is rewritten only after the next barrier, which
+// every thread reaches after its reads of that bank).  Lanes, waves and
+// wave partials are folded in the same orders as in gemv_split_kernel.
 template <class T, int ACC, int VB, int R, int U>
-__global__ void __launch_bounds__(1024) gemv_kernel(GemvArgs a)
+__global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_xs_kernel(GemvArgs a)
+{
+    constexpr int E = Elems<T, VB>::value;
+    constexpr int FL = 16 / R;  // row groups per flush
+    using V = typename Vec<VB>::type;
+    using LT = RowPartT<ACC>;
+    __shared__ LT lds[2][16][16];  // [bank][row slot][wave]
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, waves = blockDim.x >> 6;
+    const int64_t B = blockDim.x;
+    const int64_t G = gridDim.x;
+    const int64_t row_bytes = a.lda * T::bytes;
+    const int64_t tail0 = a.nvec * E;
+    const bool has_vec = a.nvec > 0;           // uniform
+    const bool has_tail = tail0 + t < a.n;     // fewer than E trailing columns
+
+    float xf[U][E];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            xf[k][e] = 0.f;
+    if (has_vec) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t v = t + k * B;
+            if (v < a.nvec)
+                load_x<E>(a.x, v, xf[k]);
+        }
+    }
+    const float xs = has_tail ? a.x[tail0 + t] : 0.f;
+
+    int j = 0;
+    for (int64_t r0 = (int64_t)blockIdx.x * R; r0 < a.m; r0 += G * R, ++j) {  // uniform
+        const char *rows[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            rows[r] = reinterpret_cast<const char *>(a.A) + min(r0 + r, a.m - 1) * row_bytes;
+        RowAcc<ACC, E> acc[R];
+        if (has_vec) {
+            V va[R][U];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    va[r][k] = load_stream<VB>(rows[r], min(t + k * B, a.nvec - 1));
+            loads_in_flight();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const bool in = t + k * B < a.nvec;
+                    float af[E];
+                    decode<T, VB>(va[r][k], af);
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+                        af[e] = in ? af[e] : 0.f;
+                    acc[r].add(af, xf[k]);
+                }
+        }
+        if (has_tail) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                acc[r].add_scalar(load_elem<T>(rows[r], tail0 + t), xs);
+        }
+        const int slot = (j % FL) * R;
+        const int bank = (j / FL) & 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const LT w = wave_row_partial<ACC, E>(acc[r]);
+            if (lane == 0)
+                lds[bank][slot + r][wave] = w;
+        }
+        if (j % FL == FL - 1 || r0 + G * R >= a.m) {  // uniform: flush the parked rows
+            __syncthreads();
+            if (t < slot + R) {
+                const int64_t row = ((int64_t)blockIdx.x + (int64_t)(j - j % FL + t / R) * G) * R + t % R;
+                if (row < a.m) {
+                    LT d = lds[bank][t][0];
+                    for (int w = 1; w < waves; ++w)
+                        d = merge(d, lds[bank][t][w]);
+                    store_row_part<ACC>(a, row, d);
+                }
+            }
+        }
+    }
+}
+
+template <class T, int ACC, int VB, int R, int U>
+__global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_kernel(GemvArgs a)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wpb = blockDim.x >> 6;
@@ -347,39 +488,47 @@ const void *gemv_pick_unroll(int unroll)
     }
 }
 
+template <class T, int ACC, int VB, int R, int U>
+const void *gemv_split_variant(bool x_stationary)
+{
+    return x_stationary ? reinterpret_cast<const void *>(&gemv_xs_kernel<T, ACC, VB, R, U>)
+                        : reinterpret_cast<const void *>(&gemv_split_kernel<T, ACC, VB, R, U>);
+}
+
 template <class T, int ACC, int VB, int R>
-const void *gemv_split_pick_unroll(int unroll)
+const void *gemv_split_pick_unroll(int unroll, bool x_stationary)
 {
     switch (unroll) {
-    case 2: return reinterpret_cast<const void *>(&gemv_split_kernel<T, ACC, VB, R, 2>);
-    case 4: return reinterpret_cast<const void *>(&gemv_split_kernel<T, ACC, VB, R, 4>);
-    case 8: return reinterpret_cast<const void *>(&gemv_split_kernel<T, ACC, VB, R, 8>);
+    case 2: return gemv_split_variant<T, ACC, VB, R, 2>(x_stationary);
+    case 4: return gemv_split_variant<T, ACC, VB, R, 4>(x_stationary);
+    case 8: return gemv_split_variant<T, ACC, VB, R, 8>(x_stationary);
     default: return nullptr;
     }
 }
 
 // Row-split instances: element loads (unaligned rows) or 16-byte loads,
-// 1 or 2 rows per iteration.
+// 1 or 2 rows per iteration, x streamed or held in registers.
 template <class T, int ACC>
-const void *gemv_split_pick(int vec_bytes, int rows, int unroll)
+const void *gemv_split_pick(int vec_bytes, int rows, int unroll, bool xs)
 {
     if (rows != 1 && rows != 2)
         return nullptr;
     if (vec_bytes == T::bytes)
-        return rows == 1 ? gemv_split_pick_unroll<T, ACC, T::bytes, 1>(unroll)
-                         : gemv_split_pick_unroll<T, ACC, T::bytes, 2>(unroll);
+        return rows == 1 ? gemv_split_pick_unroll<T, ACC, T::bytes, 1>(unroll, xs)
+                         : gemv_split_pick_unroll<T, ACC, T::bytes, 2>(unroll, xs);
     if (vec_bytes == 16)
-        return rows == 1 ? gemv_split_pick_unroll<T, ACC, 16, 1>(unroll) : gemv_split_pick_unroll<T, ACC, 16, 2>(unroll);
+        return rows == 1 ? gemv_split_pick_unroll<T, ACC, 16, 1>(unroll, xs)
+                         : gemv_split_pick_unroll<T, ACC, 16, 2>(unroll, xs);
     return nullptr;
 }
 
 template <class T>
-const void *pick_gemv_split(int acc, int vec_bytes, int rows, int unroll)
+const void *pick_gemv_split(int acc, int vec_bytes, int rows, int unroll, bool x_stationary)
 {
     switch (acc) {
-    case ACC_F32: return gemv_split_pick<T, ACC_F32>(vec_bytes, rows, unroll);
-    case ACC_COMP: return gemv_split_pick<T, ACC_COMP>(vec_bytes, rows, unroll);
-    case ACC_F64: return gemv_split_pick<T, ACC_F64>(vec_bytes, rows, unroll);
+    case ACC_F32: return gemv_split_pick<T, ACC_F32>(vec_bytes, rows, unroll, x_stationary);
+    case ACC_COMP: return gemv_split_pick<T, ACC_COMP>(vec_bytes, rows, unroll, x_stationary);
+    case ACC_F64: return gemv_split_pick<T, ACC_F64>(vec_bytes, rows, unroll, x_stationary);
     default: return nullptr;
     }
 }

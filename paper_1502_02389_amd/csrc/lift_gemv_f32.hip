@@ -8,9 +8,9 @@ const void *gemv_kernel_f32(int acc, int vec_bytes, int rows, int unroll)
     return pick_gemv<F32>(acc, vec_bytes, rows, unroll);
 }
 
-const void *gemv_split_kernel_f32(int acc, int vec_bytes, int rows, int unroll)
+const void *gemv_split_kernel_f32(int acc, int vec_bytes, int rows, int unroll, bool x_stationary)
 {
-    return pick_gemv_split<F32>(acc, vec_bytes, rows, unroll);
+    return pick_gemv_split<F32>(acc, vec_bytes, rows, unroll, x_stationary);
 }
 
 }  // namespace lift

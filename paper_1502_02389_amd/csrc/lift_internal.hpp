@@ -132,8 +132,8 @@ const void *reduce_kernel_f16(int op, int acc, int vec_bytes, int unroll);
 const void *gemv_kernel_f32(int acc, int vec_bytes, int rows, int unroll);
 const void *gemv_kernel_bf16(int acc, int vec_bytes, int rows, int unroll);
 const void *gemv_kernel_f16(int acc, int vec_bytes, int rows, int unroll);
-const void *gemv_split_kernel_f32(int acc, int vec_bytes, int rows, int unroll);
-const void *gemv_split_kernel_bf16(int acc, int vec_bytes, int rows, int unroll);
-const void *gemv_split_kernel_f16(int acc, int vec_bytes, int rows, int unroll);
+const void *gemv_split_kernel_f32(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);
+const void *gemv_split_kernel_bf16(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);
+const void *gemv_split_kernel_f16(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);
 
 }  // namespace lift

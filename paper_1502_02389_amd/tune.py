@@ -106,9 +106,9 @@ def grid(op: str, storage: str, quick: bool = False):
         vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)
         for b, v, u, r in itertools.product(blocks, vecs, (1, 2, 4, 8), (1, 2, 4)):
             yield dict(block=b, vec_bytes=v, unroll=u, rows_per_wave=r, row_split=1)
-        # a work-group per row (16-byte loads)
-        for b, u, r in itertools.product((128, 256, 512, 1024), (2, 4, 8), (1, 2)):
-            yield dict(block=b, vec_bytes=16, unroll=u, rows_per_wave=r, row_split=2)
+        # a work-group per row (16-byte loads); wg_per_cu 0 = library grid
+        for b, u, r, w in itertools.product((128, 256, 512, 1024), (2, 4, 8), (1, 2), (0, 2, 8)):
+            yield dict(block=b, vec_bytes=16, unroll=u, rows_per_wave=r, row_split=2, wg_per_cu=w)
         return
     blocks = (256, 512) if quick else (128, 256, 512, 1024)
     vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)

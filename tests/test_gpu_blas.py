@@ -317,6 +317,30 @@ def test_gemv_integer_bitexact_nonsquare_lda(gpu_device):
                     assert np.array_equal(yd.cpu().numpy().astype(np.float64), r), ("split", rows, v, u, b)
 
 
+@pytest.mark.parametrize("m,n,lda", [(20011, 37, 40), (50, 3, 4), (333, 2048, 2048)])
+def test_gemv_row_split_many_rows_per_workgroup_integer_bitexact(gpu_device, m, n, lda):
+    # wg_per_cu=1 caps the grid at one work-group per compute unit, so each
+    # work-group visits many rows (several flushes of 16 parked rows, both LDS
+    # banks, a partial last flush); n=3 has no whole vector, only the tail;
+    # n=2048 with small block * unroll streams x instead of holding it.
+    g0 = W.gen(503)
+    A = W.integers((m, lda), -8, 8, g0)
+    x = W.integers(n, -8, 8, g0)
+    y = W.integers(m, -8, 8, g0)
+    r, _ = o_gemv(1.0, A, x, 0.5, y)
+    Ad, xd = A.to(DEV), x.to(DEV)
+    for rows in (1, 2):
+        for v in (4, 16):
+            for u in (2, 8):
+                for b in (64, 256):
+                    banner("gemv row split rows", m, n, lda, rows, v, u, b)
+                    yd = y.to(DEV)
+                    L.gemv(1.0, Ad, xd, 0.5, yd, lda=lda,
+                           knobs=L.knobs(block=b, vec_bytes=v, unroll=u, rows_per_wave=rows, row_split=2,
+                                         wg_per_cu=1))
+                    assert np.array_equal(yd.cpu().numpy().astype(np.float64), r), (rows, v, u, b)
+
+
 @pytest.mark.parametrize("size", W.CONFIG3_SIZES)
 def test_gemv_config3_row_split(gpu_device, size):
     A, x, y, alpha, beta = W.config3(size)

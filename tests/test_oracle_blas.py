@@ -309,3 +309,68 @@ def test_rejects_bad_arguments():
         oracle.dot(np.zeros(3, np.float32), np.zeros(4, np.float32))
     with pytest.raises(TypeError):
         oracle.asum(np.zeros(3, np.int32))
+
+
+# ---------------------------------------------------------------- split-join form (rule 3d)
+
+PAR_THREADS = (1, 2, 3, 7, 8, 16)
+
+
+def test_split_join_integer_exact_every_split():
+    g = torch.Generator().manual_seed(6)
+    n = (1 << 18) + 5
+    x = torch.randint(-8, 9, (n,), generator=g).float().numpy()
+    y = torch.randint(-4, 5, (n,), generator=g).float().numpy()
+    want_a = float(sum(abs(int(v)) for v in x.tolist()))
+    want_d = float(sum(int(a) * int(b) for a, b in zip(x.tolist(), y.tolist())))
+    for p in PAR_THREADS:
+        assert oracle.asum_par(x, p) == want_a, p
+        assert oracle.dot_par(x, y, p) == want_d, p
+    # fewer elements than threads, empty, single element
+    for m in (0, 1, 5):
+        xs, ys = np.ascontiguousarray(x[:m]), np.ascontiguousarray(y[:m])
+        assert oracle.asum_par(xs, 8) == float(sum(abs(int(v)) for v in xs.tolist()))
+        assert oracle.dot_par(xs, ys, 8) == float(sum(int(a) * int(b) for a, b in zip(xs.tolist(), ys.tolist())))
+
+
+def test_split_join_one_chunk_is_the_sequential_form():
+    g = torch.Generator().manual_seed(7)
+    x = (torch.rand(100_003, generator=g) * 2 - 1).numpy()
+    y = (torch.rand(100_003, generator=g) * 2 - 1).numpy()
+    assert oracle.asum_par(x, 1) == oracle.asum(x)
+    assert oracle.dot_par(x, y, 1) == oracle.dot(x, y)
+
+
+@pytest.mark.parametrize("p", PAR_THREADS)
+def test_split_join_within_bound_of_fsum(p):
+    g = torch.Generator().manual_seed(8)
+    t = (torch.rand(60_001, generator=g) * 2 - 1)
+    x = t.numpy()
+    y = (torch.rand(60_001, generator=g) * 2 - 1).numpy()
+    vals = x.astype(np.float64)
+    exact = math.fsum(abs(v) for v in vals)
+    # each term passes through at most (chunk - 1) + (p - 1) <= n - 1 additions
+    assert abs(oracle.asum_par(x, p) - exact) <= seq_bound(exact, len(vals)) + U * exact
+    prods = [float(a) * float(b) for a, b in zip(x.tolist(), y.tolist())]
+    ed, mass = math.fsum(prods), math.fsum(abs(q) for q in prods)
+    assert abs(oracle.dot_par(x, y, p) - ed) <= seq_bound(mass, len(prods)) + U * abs(ed)
+
+
+def test_split_join_16bit_storage_and_scal_map():
+    g = torch.Generator().manual_seed(9)
+    t = torch.randint(-8, 9, (40_000,), generator=g).to(torch.bfloat16)
+    xb = t.view(torch.int16).numpy().view(np.uint16)
+    want = float(sum(abs(int(v)) for v in t.float().tolist()))
+    for p in (3, 8):
+        assert oracle.asum_par(xb, p, dtype="bf16") == want
+    xf = (torch.rand(50_001, generator=g) * 2 - 1).numpy()
+    want_s = xf.astype(np.float64) * 2.5                  # exact: binary32 x 2.5 fits binary64
+    for p in PAR_THREADS:
+        assert np.array_equal(oracle.scal_par(2.5, xf, p), want_s), p
+
+
+def test_split_join_rejects_bad_thread_counts():
+    x = np.ones(4, np.float32)
+    for p in (0, -1, 257):
+        with pytest.raises(RuntimeError):
+            oracle.asum_par(x, p)

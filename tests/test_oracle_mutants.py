@@ -34,6 +34,11 @@ MUTANTS = {
     "f16_subnormal_scale": ("ldexp((double)m, -24)", "ldexp((double)m, -25)"),
     "bf16_wrong_shift": ("(uint32_t)h << 16", "(uint32_t)h << 15"),
     "zip_swaps_pairs": ("out[i].a = a[i];\n        out[i].b = b[i];", "out[i].a = a[i];\n        out[i].b = a[i];"),
+    "split_join_drops_last_chunk": ("for (int64_t i = 0; i < p; ++i)\n            acc = fn_add(acc, c[i].partial, NULL);",
+                                    "for (int64_t i = 0; i + 1 < p; ++i)\n            acc = fn_add(acc, c[i].partial, NULL);"),
+    "split_join_byte_offsets": ("c[i].x = (const char *)x + (size_t)lo * elem_size(xt);",
+                                "c[i].x = (const char *)x + (size_t)lo;"),
+    "split_join_chunk_too_short": ("int64_t k = n > 0 ? (n + p - 1) / p : 0;", "int64_t k = n > 0 ? n / p : 0;"),
 }
 
 FAST_PINS = [
@@ -50,6 +55,8 @@ FAST_PINS = [
     pins.test_gemv_alpha_zero_and_beta_zero,
     pins.test_gemv_brute_force_rational_nonsquare_with_lda,
     pins.test_gemv_absmass_definition,
+    pins.test_split_join_integer_exact_every_split,
+    pins.test_split_join_16bit_storage_and_scal_map,
 ]
 
 
@@ -62,7 +69,7 @@ def _build(src: str, path: str):
     c = path + ".c"
     with open(c, "w") as f:
         f.write(src)
-    subprocess.run(["gcc", "-O1", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", path, c, "-lm"],
+    subprocess.run(["gcc", "-O1", "-std=c99", "-ffp-contract=off", "-pthread", "-fPIC", "-shared", "-o", path, c, "-lm"],
                    check=True)
 
 
