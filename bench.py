@@ -110,8 +110,8 @@ def main():
     log("device", props.name, "CUs", props.multi_processor_count, "lib", L.lift_version())
 
     # ------------------------------------------------------------ main step
-    n = W.CONFIG2_N
-    x_cpu, y_cpu, alpha = W.config2(n)
+    n = W.STREAM_N
+    x_cpu, y_cpu, alpha = W.stream_vectors(n)
     x0, y0 = x_cpu.to(dev), y_cpu.to(dev)
     set_bytes = 5 * 4 * n
     nsets = max(2, -(-COLD_BYTES // set_bytes))
@@ -311,8 +311,8 @@ def forms(L, W, dev, stream):
         log("form", name, out[name])
 
     # gemv fp32, square 4096 and 8192, and 16384 (A 1 GiB) for the large-size roofline
-    for size in W.CONFIG3_SIZES + (16384,):
-        A, x, y, alpha, beta = W.config3(size)
+    for size in W.GEMV_SIZES + (16384,):
+        A, x, y, alpha, beta = W.gemv_square(size)
         nb = 4 * size * size + 4 * size + 8 * size
         ns = max(2, -(-COLD_BYTES // nb))
         As = [A.to(dev) for _ in range(ns)]
@@ -326,9 +326,9 @@ def forms(L, W, dev, stream):
         torch.cuda.empty_cache()
 
     # 16-bit storage asum / dot, n = 2^26
-    n = W.CONFIG4_N
+    n = W.HALF_N
     for storage, code in (("bf16", L.LIFT_BF16), ("f16", L.LIFT_F16)):
-        x, y = W.config4_vectors(storage)
+        x, y = W.half_vectors(storage)
         ns = max(2, -(-COLD_BYTES // (4 * n)))
         xs = [x.to(dev) for _ in range(ns)]
         ys = [y.to(dev) for _ in range(ns)]
@@ -352,7 +352,7 @@ def forms(L, W, dev, stream):
         torch.cuda.empty_cache()
 
     # bf16 gemv 16384^2 (A 512 MiB: larger than the Infinity Cache by itself)
-    A, x, y, alpha, beta = W.config4_gemv()
+    A, x, y, alpha, beta = W.half_gemv()
     size = A.shape[0]
     Ad, xd, yd = A.to(dev), x.to(dev), y.to(dev)
     nb = 2 * size * size + 4 * size + 8 * size
@@ -372,7 +372,7 @@ def batch_form(L, W, dev, stream, storage):
     import torch
 
     lib = L.library()
-    spec = W.config5_shapes()
+    spec = W.batch_shapes()
     dt = {"f32": torch.float32, "bf16": torch.bfloat16}[storage]
     g = torch.Generator(device=dev)
     g.manual_seed(5)
@@ -471,7 +471,7 @@ def batch_form(L, W, dev, stream, storage):
            "knobs": "tuned" if tuned is not None else "default"}
     log("form batch", storage, rec)
     b.close()
-    return {f"batch_{storage}_config5": rec}
+    return {f"batch_{storage}_4096red_256gemv": rec}
 
 
 if __name__ == "__main__":

@@ -132,7 +132,7 @@ class BatchOperands:
 
         self.op, self.storage = "batch", storage
         dev = torch.device("cuda:0")
-        spec = W.config5_shapes()
+        spec = W.batch_shapes()
         dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[storage]
         g = torch.Generator(device=dev)
         g.manual_seed(seed)

@@ -92,7 +92,7 @@ def check(cpu, batch, problems, bound, exact=False):
 
 
 def small_spec(seed=40, n_red=240, n_gemv=24):
-    return W.config5_shapes(n_red=n_red, n_gemv=n_gemv, lo_exp=0.0, hi_exp=17.0, mn_lo=1, mn_hi=700, seed=seed)
+    return W.batch_shapes(n_red=n_red, n_gemv=n_gemv, lo_exp=0.0, hi_exp=17.0, mn_lo=1, mn_hi=700, seed=seed)
 
 
 def test_batch_small_mixed_f32(gpu_device):
@@ -200,10 +200,10 @@ def test_batch_graph_replays_match_eager(gpu_device):
     b.close()
 
 
-def test_batch_config5_full_size_sampled(gpu_device):
-    spec = W.config5_shapes()
-    banner("batch config5 full size f32")
-    reds, gemvs = W.config5_values(spec, "f32")
+def test_batch_full_size_sampled(gpu_device):
+    spec = W.batch_shapes()
+    banner("batch 4096 reductions + 256 gemv, full size, f32")
+    reds, gemvs = W.batch_values(spec, "f32")
     problems = []
     for kind, x, y in reds:
         problems.append(("dot", x.to(DEV), y.to(DEV)) if kind == "dot" else ("asum", x.to(DEV)))

@@ -33,17 +33,17 @@ def sync():
 # ------------------------------------------------------------------ asum
 
 
-def test_asum_config1_uniform(gpu_device):
-    x = W.config1()
-    banner("asum config1 uniform n", x.numel())
+def test_asum_2p20_uniform(gpu_device):
+    x = W.asum_small_vector()
+    banner("asum uniform n", x.numel())
     g = L.asum(x.to(DEV)).item()
     r = o_asum(x)
     assert rel(g, r) <= TOL, (g, r)
 
 
-def test_asum_config1_integer_bitexact(gpu_device):
-    x = W.config1(integer=True)
-    banner("asum config1 integers n", x.numel())
+def test_asum_2p20_integer_bitexact(gpu_device):
+    x = W.asum_small_vector(integer=True)
+    banner("asum integers n", x.numel())
     g = L.asum(x.to(DEV)).item()
     assert g == o_asum(x) == float(x.abs().sum().item())
 
@@ -82,17 +82,17 @@ def test_asum_special_values(gpu_device):
 # ------------------------------------------------------------------ dot
 
 
-def test_dot_config2(gpu_device):
-    x, y, _ = W.config2()
-    banner("dot config2 n", x.numel())
+def test_dot_2p24(gpu_device):
+    x, y, _ = W.stream_vectors()
+    banner("dot n", x.numel())
     g = L.dot(x.to(DEV), y.to(DEV)).item()
     r, mass = o_dot(x, y)
     assert abs(g - r) <= TOL * mass, (g, r, mass)
 
 
-def test_asum_config2(gpu_device):
-    x, _, _ = W.config2()
-    banner("asum config2 n", x.numel())
+def test_asum_2p24(gpu_device):
+    x, _, _ = W.stream_vectors()
+    banner("asum n", x.numel())
     assert rel(L.asum(x.to(DEV)).item(), o_asum(x)) <= TOL
 
 
@@ -171,7 +171,7 @@ def test_grid_capped_at_max_workgroups(gpu_device):
 
 
 def test_reduce_bitwise_deterministic(gpu_device):
-    x = W.config1().to(DEV)
+    x = W.asum_small_vector().to(DEV)
     y = W.uniform(x.numel(), W.gen(9)).to(DEV)
     banner("determinism")
     a0 = L.asum(x)
@@ -183,7 +183,7 @@ def test_reduce_bitwise_deterministic(gpu_device):
 
 
 def test_workspace_zero_after_calls_and_poisoned_slots(gpu_device):
-    x = W.config1()
+    x = W.asum_small_vector()
     ws = L.workspace(torch.device(DEV))
     banner("workspace reset")
     r = o_asum(x)
@@ -200,7 +200,7 @@ def test_workspace_zero_after_calls_and_poisoned_slots(gpu_device):
 
 
 def test_result_f64_and_raw_entry_point(gpu_device):
-    x = W.config1(integer=True)
+    x = W.asum_small_vector(integer=True)
     xd = x.to(DEV)
     banner("raw entry point")
     res = torch.zeros((), dtype=torch.float32, device=DEV)
@@ -219,9 +219,9 @@ def _scal_check(x: torch.Tensor, alpha: float, got: torch.Tensor):
     assert np.array_equal(got.cpu().numpy().view(np.uint32), want.view(np.uint32))
 
 
-def test_scal_config2_bitexact(gpu_device):
-    x, _, alpha = W.config2()
-    banner("scal config2")
+def test_scal_2p24_bitexact(gpu_device):
+    x, _, alpha = W.stream_vectors()
+    banner("scal 2^24")
     _scal_check(x, alpha, L.scal(alpha, x.to(DEV)))
 
 
@@ -280,10 +280,10 @@ def _gemv_check(alpha, A, x, beta, y0, got, n=None, tol=TOL):
     assert np.all(err <= tol * mass + 1e-30), (float(np.max(err / np.maximum(mass, 1e-300))))
 
 
-@pytest.mark.parametrize("size", W.CONFIG3_SIZES)
-def test_gemv_config3(gpu_device, size):
-    A, x, y, alpha, beta = W.config3(size)
-    banner("gemv config3", size)
+@pytest.mark.parametrize("size", W.GEMV_SIZES)
+def test_gemv_square(gpu_device, size):
+    A, x, y, alpha, beta = W.gemv_square(size)
+    banner("gemv square", size)
     yd = y.to(DEV)
     L.gemv(alpha, A.to(DEV), x.to(DEV), beta, yd)
     _gemv_check(alpha, A, x, beta, y, yd)
@@ -341,10 +341,10 @@ def test_gemv_row_split_many_rows_per_workgroup_integer_bitexact(gpu_device, m, 
                     assert np.array_equal(yd.cpu().numpy().astype(np.float64), r), (rows, v, u, b)
 
 
-@pytest.mark.parametrize("size", W.CONFIG3_SIZES)
-def test_gemv_config3_row_split(gpu_device, size):
-    A, x, y, alpha, beta = W.config3(size)
-    banner("gemv config3 row split", size)
+@pytest.mark.parametrize("size", W.GEMV_SIZES)
+def test_gemv_square_row_split(gpu_device, size):
+    A, x, y, alpha, beta = W.gemv_square(size)
+    banner("gemv square row split", size)
     Ad, xd = A.to(DEV), x.to(DEV)
     for rows, u in ((1, 8), (2, 4)):
         yd = y.to(DEV)

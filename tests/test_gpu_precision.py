@@ -26,7 +26,7 @@ BOUND = {"f32": 1e-5, "comp": 1e-6, "f64combine": 1e-5}
 @pytest.fixture(scope="module", params=["bf16", "f16"])
 def vectors(request):
     storage = request.param
-    x, y = W.config4_vectors(storage)
+    x, y = W.half_vectors(storage)
     ra = o_asum(x)
     rd, mass = o_dot(x, y)
     return storage, x, y, ra, rd, mass
@@ -34,9 +34,9 @@ def vectors(request):
 
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("rt", [torch.float32, torch.float64])
-def test_config4_asum_dot(gpu_device, vectors, acc, rt):
+def test_16bit_2p26_asum_dot(gpu_device, vectors, acc, rt):
     storage, x, y, ra, rd, mass = vectors
-    banner("config4", storage, acc, rt)
+    banner("16-bit 2^26", storage, acc, rt)
     xd, yd = x.to(DEV), y.to(DEV)
     ga = L.asum(xd, acc=acc, result_dtype=rt).item()
     gd = L.dot(xd, yd, acc=acc, result_dtype=rt).item()
@@ -85,7 +85,7 @@ def test_compensated_beats_plain_on_adversarial_input(gpu_device):
 def test_f64combine_result_carries_more_digits(gpu_device):
     # many work-group partials of different magnitude: binary64 combine with a
     # binary64 result is at least as close as the binary32 combine
-    x, _ = W.config4_vectors("bf16", n=1 << 24)
+    x, _ = W.half_vectors("bf16", n=1 << 24)
     r = o_asum(x)
     xd = x.to(DEV)
     banner("f64 combine")
@@ -95,9 +95,9 @@ def test_f64combine_result_carries_more_digits(gpu_device):
 
 
 @pytest.mark.parametrize("acc", ACCS)
-def test_config4_gemv_bf16(gpu_device, acc):
+def test_half_gemv_bf16(gpu_device, acc):
     A, x, y, alpha, beta = _gemv_operands()
-    banner("config4 gemv bf16", acc)
+    banner("bf16 gemv 16384", acc)
     yd = y.to(DEV)
     L.gemv(alpha, _gemv_dev(A), x.to(DEV), beta, yd, acc=acc)
     r, mass = _gemv_ref()
@@ -139,7 +139,7 @@ _G = {}
 
 def _gemv_operands():
     if "ops" not in _G:
-        _G["ops"] = W.config4_gemv()
+        _G["ops"] = W.half_gemv()
     return _G["ops"]
 
 

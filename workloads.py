@@ -47,45 +47,45 @@ def integers(shape, lo: int, hi: int, g: torch.Generator, storage: str = "f32") 
 
 
 # --------------------------------------------------------------------------
-# the five workload configurations
+# the workloads: sizes and value recipes
 # --------------------------------------------------------------------------
 
-CONFIG1_N = 1 << 20            # asum, single vector
-CONFIG2_N = 1 << 24            # scal/asum/dot, 64 MiB per fp32 vector
-CONFIG2_ALPHA = 2.5
-CONFIG3_SIZES = (4096, 8192)   # square gemv
-CONFIG3_ALPHA, CONFIG3_BETA = 1.0, 0.5
-CONFIG4_N = 1 << 26            # 16-bit storage asum/dot
-CONFIG4_GEMV = 16384           # bf16 A, square
-CONFIG5_NRED, CONFIG5_NGEMV = 4096, 256
+ASUM_SMALL_N = 1 << 20      # asum, single vector
+STREAM_N = 1 << 24          # scal/asum/dot, 64 MiB per fp32 vector
+STREAM_ALPHA = 2.5
+GEMV_SIZES = (4096, 8192)   # square gemv
+GEMV_ALPHA, GEMV_BETA = 1.0, 0.5
+HALF_N = 1 << 26            # 16-bit storage asum/dot
+HALF_GEMV = 16384           # bf16 A, square
+BATCH_NRED, BATCH_NGEMV = 4096, 256
 
 
-def config1(integer: bool = False):
+def asum_small_vector(integer: bool = False):
     """asum, n = 2^20, seed 0: uniform, or integers in [-8, 8]."""
     g = gen(0)
     if integer:
-        return integers(CONFIG1_N, -8, 8, g)
-    return uniform(CONFIG1_N, g)
+        return integers(ASUM_SMALL_N, -8, 8, g)
+    return uniform(ASUM_SMALL_N, g)
 
 
-def config2(n: int = CONFIG2_N):
+def stream_vectors(n: int = STREAM_N):
     """scal/asum/dot vectors x then y, uniform, seed 1; alpha = 2.5."""
     g = gen(1)
     x = uniform(n, g)
     y = uniform(n, g)
-    return x, y, CONFIG2_ALPHA
+    return x, y, STREAM_ALPHA
 
 
-def config3(size: int):
+def gemv_square(size: int):
     """gemv operands A (size x size), x, y ~ normal(0, 1), seed 2."""
     g = gen(2)
     A = normal((size, size), g)
     x = normal(size, g)
     y = normal(size, g)
-    return A, x, y, CONFIG3_ALPHA, CONFIG3_BETA
+    return A, x, y, GEMV_ALPHA, GEMV_BETA
 
 
-def config4_vectors(storage: str, n: int = CONFIG4_N):
+def half_vectors(storage: str, n: int = HALF_N):
     """16-bit-stored x, y for asum/dot, uniform, seed 3."""
     g = gen(3)
     x = uniform(n, g, storage)
@@ -93,13 +93,13 @@ def config4_vectors(storage: str, n: int = CONFIG4_N):
     return x, y
 
 
-def config4_gemv(size: int = CONFIG4_GEMV):
+def half_gemv(size: int = HALF_GEMV):
     """bf16-stored A with fp32 x, y ~ normal, seed 3; alpha 1, beta 0.5."""
     g = gen(3)
     A = normal((size, size), g, "bf16")
     x = normal(size, g)
     y = normal(size, g)
-    return A, x, y, CONFIG3_ALPHA, CONFIG3_BETA
+    return A, x, y, GEMV_ALPHA, GEMV_BETA
 
 
 @dataclass
@@ -111,9 +111,9 @@ class BatchSpec:
     gemv_mn: list = field(default_factory=list)    # (m, n)
 
 
-def config5_shapes(n_red: int = CONFIG5_NRED, n_gemv: int = CONFIG5_NGEMV,
-                   lo_exp: float = 8.0, hi_exp: float = 20.0,
-                   mn_lo: int = 64, mn_hi: int = 4096, seed: int = 4) -> BatchSpec:
+def batch_shapes(n_red: int = BATCH_NRED, n_gemv: int = BATCH_NGEMV,
+                 lo_exp: float = 8.0, hi_exp: float = 20.0,
+                 mn_lo: int = 64, mn_hi: int = 4096, seed: int = 4) -> BatchSpec:
     """Reduction lengths floor(2^U(lo, hi)) (log-uniform), kinds alternating
     dot (even index) / asum (odd index); gemv M, N uniform in [mn_lo, mn_hi]."""
     g = gen(seed)
@@ -124,7 +124,7 @@ def config5_shapes(n_red: int = CONFIG5_NRED, n_gemv: int = CONFIG5_NGEMV,
     return BatchSpec(kinds, lens, [(int(a), int(b)) for a, b in mn])
 
 
-def config5_values(spec: BatchSpec, storage: str = "f32", seed: int = 5):
+def batch_values(spec: BatchSpec, storage: str = "f32", seed: int = 5):
     """Values for a batch: reductions uniform, gemv normal (A, x, y per problem)."""
     g = gen(seed)
     reds = []
