@@ -10,7 +10,8 @@ Two independent implementations of the same definitions live here:
 * ``lift_oracle.c`` (built with gcc into ``liboracle.so``): scal, asum, dot
   and gemv as the literal compositions of the paper's BLAS figure (Fig. 5),
   evaluated in binary64 with a sequential left fold for ``reduce`` -- the
-  full-size numeric oracle;
+  full-size numeric oracle -- and BlackScholes as map(BSComputation) over
+  stock prices (Section 5.2, closed-form model);
 * ``patterns.py``: the paper's patterns (Tables 1 and 2) as Python functions,
   used for the rewrite-rule, derivation and low-level-expression pins.
 
@@ -70,9 +71,10 @@ def _configure(lib):
     lib.oracle_scal_par.argtypes = [i64, dbl, i32, vp, dp, i32]
     lib.oracle_asum_par.argtypes = [i64, i32, vp, dp, i32]
     lib.oracle_dot_par.argtypes = [i64, i32, vp, i32, vp, dp, i32]
+    lib.oracle_blackscholes.argtypes = [i64, i32, vp, dbl, dbl, dbl, dbl, dp]
     for name in ("oracle_widen", "oracle_scal", "oracle_asum", "oracle_dot",
                  "oracle_dot_absmass", "oracle_gemv", "oracle_gemv_absmass",
-                 "oracle_scal_par", "oracle_asum_par", "oracle_dot_par"):
+                 "oracle_scal_par", "oracle_asum_par", "oracle_dot_par", "oracle_blackscholes"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -239,3 +241,15 @@ def dot_par(x: np.ndarray, y: np.ndarray, threads: int, dtype=None, ydtype=None)
     _check(_load().oracle_dot_par(x.size, _code(x, dtype), _ptr(x), _code(y, ydtype if ydtype else dtype),
                                   _ptr(y), ctypes.byref(r), int(threads)), "dot_par")
     return r.value
+
+
+# ---------------------------------------------------------------- BlackScholes
+def blackscholes(s: np.ndarray, strike: float, rate: float, volatility: float, years: float,
+                 dtype=None) -> np.ndarray:
+    """map(BSComputation) over stock prices: an (n, 2) array of {call, put}."""
+    s = _flat(s)
+    out = np.empty((s.size, 2), dtype=np.float64)
+    _check(_load().oracle_blackscholes(s.size, _code(s, dtype), _ptr(s), float(strike), float(rate),
+                                       float(volatility), float(years),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "blackscholes")
+    return out

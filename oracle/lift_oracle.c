@@ -454,3 +454,77 @@ int oracle_dot_par(int64_t n, int xt, const void *x, int yt, const void *y, doub
 {
     return split_join(PAR_DOT, n, xt, x, yt, y, 0.0, NULL, result, threads);
 }
+
+/* ------------------------------------------------------------------ */
+/* BlackScholes: map(BSComputation) over stock prices (Section 5.2)    */
+/* ------------------------------------------------------------------ */
+/*
+ * The paper maps BSComputation over a vector of stock prices s; for each s
+ * it computes d1 = compD1(s), d2 = compD2(d1, s) and returns the pair
+ * {compCall(d1, d2, s), compPut(d1, d2, s)}.  The four helpers are not
+ * printed; they are the closed-form Black-Scholes model for a European
+ * option with strike K, time to expiry T (years), risk-free rate r and
+ * volatility v, the same for every element:
+ *
+ *   d1   = (ln(s / K) + (r + v^2 / 2) T) / (v sqrt(T))
+ *   d2   = d1 - v sqrt(T)
+ *   call = s N(d1) - K exp(-r T) N(d2)
+ *   put  = K exp(-r T) N(-d2) - s N(-d1)
+ *
+ * with N the standard normal distribution function, N(x) = erfc(-x/sqrt 2)/2.
+ * Output: pairs {call, put}, element i at out[2i], out[2i + 1].
+ */
+typedef struct { double K, r, v, T; } bs_params;
+
+static double cnd(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+static double comp_d1(double s, const bs_params *q)
+{
+    return (log(s / q->K) + (q->r + 0.5 * q->v * q->v) * q->T) / (q->v * sqrt(q->T));
+}
+
+static double comp_d2(double d1, double s, const bs_params *q)
+{
+    (void)s;
+    return d1 - q->v * sqrt(q->T);
+}
+
+static double comp_call(double d1, double d2, double s, const bs_params *q)
+{
+    return s * cnd(d1) - q->K * exp(-q->r * q->T) * cnd(d2);
+}
+
+static double comp_put(double d1, double d2, double s, const bs_params *q)
+{
+    return q->K * exp(-q->r * q->T) * cnd(-d2) - s * cnd(-d1);
+}
+
+/* BSComputation(s) = {compCall(d1, d2, s), compPut(d1, d2, s)} */
+static pair_t bs_computation(double s, const bs_params *q)
+{
+    double d1 = comp_d1(s, q);
+    double d2 = comp_d2(d1, s, q);
+    pair_t r = {comp_call(d1, d2, s, q), comp_put(d1, d2, s, q)};
+    return r;
+}
+
+int oracle_blackscholes(int64_t n, int st, const void *s, double strike, double rate, double volatility,
+                        double years, double *out)
+{
+    if (n < 0 || !valid_dtype(st) || (n > 0 && (!s || !out)))
+        return OR_EINVAL;
+    if (!(strike > 0) || !(volatility > 0) || !(years > 0) || !isfinite(rate))
+        return OR_EINVAL;
+    double *w = malloc((size_t)(n ? n : 1) * sizeof *w);
+    if (!w)
+        return OR_ENOMEM;
+    widen(n, st, s, 1, w);
+    bs_params q = {strike, rate, volatility, years};
+    for (int64_t i = 0; i < n; ++i) {   /* map(BSComputation) */
+        pair_t cp = bs_computation(w[i], &q);
+        out[2 * i] = cp.a;
+        out[2 * i + 1] = cp.b;
+    }
+    free(w);
+    return OR_OK;
+}

@@ -13,6 +13,7 @@ import subprocess
 import pytest
 
 import oracle
+from tests import test_oracle_blackscholes as bs
 from tests import test_oracle_blas as pins
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "lift_oracle.c")).read()
@@ -39,6 +40,12 @@ MUTANTS = {
     "split_join_byte_offsets": ("c[i].x = (const char *)x + (size_t)lo * elem_size(xt);",
                                 "c[i].x = (const char *)x + (size_t)lo;"),
     "split_join_chunk_too_short": ("int64_t k = n > 0 ? (n + p - 1) / p : 0;", "int64_t k = n > 0 ? n / p : 0;"),
+    "bs_d2_adds_spread": ("return d1 - q->v * sqrt(q->T);", "return d1 + q->v * sqrt(q->T);"),
+    "bs_drops_half_variance": ("(q->r + 0.5 * q->v * q->v) * q->T)", "(q->r) * q->T)"),
+    "bs_put_wrong_tail": ("* cnd(-d2) - s * cnd(-d1);", "* cnd(d2) - s * cnd(-d1);"),
+    "bs_call_undiscounted": ("return s * cnd(d1) - q->K * exp(-q->r * q->T) * cnd(d2);",
+                             "return s * cnd(d1) - q->K * cnd(d2);"),
+    "bs_cnd_wrong_scale": ("0.5 * erfc(-x / sqrt(2.0))", "0.5 * erfc(-x / 2.0)"),
 }
 
 FAST_PINS = [
@@ -57,6 +64,9 @@ FAST_PINS = [
     pins.test_gemv_absmass_definition,
     pins.test_split_join_integer_exact_every_split,
     pins.test_split_join_16bit_storage_and_scal_map,
+    bs.test_put_call_parity_and_homogeneity,
+    bs.test_at_the_forward_call_equals_put,
+    bs.test_matches_numerical_integration_all_cases,
 ]
 
 

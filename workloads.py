@@ -58,6 +58,8 @@ GEMV_ALPHA, GEMV_BETA = 1.0, 0.5
 HALF_N = 1 << 26            # 16-bit storage asum/dot
 HALF_GEMV = 16384           # bf16 A, square
 BATCH_NRED, BATCH_NGEMV = 4096, 256
+BS_N = 1 << 22              # BlackScholes: "4 million" stock prices
+BS_STRIKE, BS_RATE, BS_VOLATILITY, BS_YEARS = 20.0, 0.02, 0.30, 1.0
 
 
 def asum_small_vector(integer: bool = False):
@@ -139,3 +141,12 @@ def batch_values(spec: BatchSpec, storage: str = "f32", seed: int = 5):
         y = normal(m, g)
         gemvs.append((A, x, y))
     return reds, gemvs
+
+
+def blackscholes_prices(n: int = BS_N, seed: int = 6):
+    """Stock prices ~ U[5, 30) in fp32 (around the strike of 20: in, at and
+    out of the money), seed 6; returns the prices and (strike, rate,
+    volatility, years)."""
+    g = gen(seed)
+    s = torch.rand(n, generator=g, dtype=torch.float32) * 25 + 5
+    return s, (BS_STRIKE, BS_RATE, BS_VOLATILITY, BS_YEARS)
