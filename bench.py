@@ -21,11 +21,12 @@ Also reported on the same JSON line:
                  split-join form on the host cores (value) and sequentially on
                  one thread; each timed for a bounded number of seconds
   kernels      : per-kernel average durations from back-to-back launches
-  forms        : gemv fp32 (4096^2, 8192^2, 16384^2), 16-bit storage (n = 2^26 asum/dot,
+  forms        : BlackScholes over 2^22 prices, gemv fp32 (4096^2, 8192^2,
+                 16384^2), 16-bit storage (n = 2^26 asum/dot,
                  bf16 gemv 16384^2) in each accumulation variant, as GB/s and
                  binary32-equivalent GB/s
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-forms]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-forms] [--forms LIST]
        [--no-cpu-baseline] [--cpu-seconds S]
 """
 from __future__ import annotations
@@ -44,6 +45,7 @@ sys.path.insert(0, ROOT)
 PEAK_GBS = 8000.0
 METRIC = "HBM GB/s and % of 8 TB/s peak: asum/dot/gemv FP32 vs BF16 and batched forms"
 COLD_BYTES = 1 << 30          # rotate buffer sets until at least this much is touched
+FORMS = ("gemv", "half", "batch", "blackscholes", "gemv16")
 
 
 def log(*a):
@@ -84,6 +86,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--forms", default=",".join(FORMS),
+                    help="forms to run: " + ", ".join(FORMS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--event-every", type=int, default=10,
@@ -231,7 +235,7 @@ def main():
     if not args.no_forms:
         del sets, ptr
         torch.cuda.empty_cache()
-        result["forms"] = forms(L, W, dev, stream)
+        result["forms"] = forms(L, W, dev, stream, tuple(args.forms.split(",")))
 
     print(json.dumps(result), flush=True)
 
@@ -295,7 +299,7 @@ def _time_calls(fn, nsets, stream, reps=50, warm=5):
     return e0.elapsed_time(e1) * 1e3 / reps
 
 
-def forms(L, W, dev, stream):
+def forms(L, W, dev, stream, which=FORMS):
     import torch
 
     lib = L.library()
@@ -310,63 +314,82 @@ def forms(L, W, dev, stream):
                      "fp32_equiv_GB_s": round(fp32_bytes / (us * 1e-6) / 1e9, 1)}
         log("form", name, out[name])
 
-    # gemv fp32, square 4096 and 8192, and 16384 (A 1 GiB) for the large-size roofline
-    for size in W.GEMV_SIZES + (16384,):
-        A, x, y, alpha, beta = W.gemv_square(size)
-        nb = 4 * size * size + 4 * size + 8 * size
-        ns = max(2, -(-COLD_BYTES // nb))
-        As = [A.to(dev) for _ in range(ns)]
-        xd, yd = x.to(dev), y.to(dev)
+    if "gemv" in which:
+        # gemv fp32, square 4096 and 8192, and 16384 (A 1 GiB) for the large-size roofline
+        for size in W.GEMV_SIZES + (16384,):
+            A, x, y, alpha, beta = W.gemv_square(size)
+            nb = 4 * size * size + 4 * size + 8 * size
+            ns = max(2, -(-COLD_BYTES // nb))
+            As = [A.to(dev) for _ in range(ns)]
+            xd, yd = x.to(dev), y.to(dev)
 
-        def call(i, As=As, xd=xd, yd=yd, size=size, alpha=alpha, beta=beta):
-            st = lib.lift_gemv(size, size, alpha, As[i].data_ptr(), size, xd.data_ptr(), beta, yd.data_ptr(), sh)
-            assert st == 0
-        rec(f"gemv_f32_{size}", _time_calls(call, ns, stream), nb, nb)
-        del As
+            def call(i, As=As, xd=xd, yd=yd, size=size, alpha=alpha, beta=beta):
+                st = lib.lift_gemv(size, size, alpha, As[i].data_ptr(), size, xd.data_ptr(), beta, yd.data_ptr(), sh)
+                assert st == 0
+            rec(f"gemv_f32_{size}", _time_calls(call, ns, stream), nb, nb)
+            del As
+            torch.cuda.empty_cache()
+
+    if "half" in which:
+        # 16-bit storage asum / dot, n = 2^26
+        n = W.HALF_N
+        for storage, code in (("bf16", L.LIFT_BF16), ("f16", L.LIFT_F16)):
+            x, y = W.half_vectors(storage)
+            ns = max(2, -(-COLD_BYTES // (4 * n)))
+            xs = [x.to(dev) for _ in range(ns)]
+            ys = [y.to(dev) for _ in range(ns)]
+            res = torch.zeros((), dtype=torch.float64, device=dev)
+            for acc_name, acc in (("f32", 0), ("comp", 1), ("f64combine", 2)):
+                def ca(i, acc=acc):
+                    assert lib.lift_asum_ex(n, code, xs[i].data_ptr(), acc, L.LIFT_F64, res.data_ptr(), wsp, wsb,
+                                            None, sh) == 0
+
+                def cd(i, acc=acc):
+                    assert lib.lift_dot_ex(n, code, xs[i].data_ptr(), ys[i].data_ptr(), acc, L.LIFT_F64,
+                                           res.data_ptr(), wsp, wsb, None, sh) == 0
+                rec(f"asum_{storage}_{acc_name}_2^26", _time_calls(ca, ns, stream), 2 * n, 4 * n)
+                rec(f"dot_{storage}_{acc_name}_2^26", _time_calls(cd, ns, stream), 4 * n, 8 * n)
+            del xs, ys
+            torch.cuda.empty_cache()
+
+    if "batch" in which:
+        # batched form (4096 reductions + 256 gemv) vs the same problems per call
+        for storage in ("f32", "bf16"):
+            out.update(batch_form(L, W, dev, stream, storage))
+            torch.cuda.empty_cache()
+
+    if "blackscholes" in which:
+        # BlackScholes over 2^22 stock prices: 4 B in, 8 B ({call, put}) out per price
+        s_cpu, params = W.blackscholes_prices()
+        n = s_cpu.numel()
+        ns = max(2, -(-COLD_BYTES // (12 * n)))
+        ss = [s_cpu.to(dev) for _ in range(ns)]
+        outs = [torch.empty((n, 2), device=dev) for _ in range(ns)]
+
+        def cb(i):
+            assert lib.lift_blackscholes(n, ss[i].data_ptr(), *params, outs[i].data_ptr(), sh) == 0
+        rec("blackscholes_f32_2^22", _time_calls(cb, ns, stream), 12 * n, 12 * n)
+        out["blackscholes_f32_2^22"]["options_per_s"] = round(n / (out["blackscholes_f32_2^22"]["avg_us"] * 1e-6), 1)
+        del ss, outs
         torch.cuda.empty_cache()
 
-    # 16-bit storage asum / dot, n = 2^26
-    n = W.HALF_N
-    for storage, code in (("bf16", L.LIFT_BF16), ("f16", L.LIFT_F16)):
-        x, y = W.half_vectors(storage)
-        ns = max(2, -(-COLD_BYTES // (4 * n)))
-        xs = [x.to(dev) for _ in range(ns)]
-        ys = [y.to(dev) for _ in range(ns)]
-        res = torch.zeros((), dtype=torch.float64, device=dev)
+    if "gemv16" in which:
+        # bf16 gemv 16384^2 (A 512 MiB: larger than the Infinity Cache by itself)
+        A, x, y, alpha, beta = W.half_gemv()
+        size = A.shape[0]
+        Ad, xd, yd = A.to(dev), x.to(dev), y.to(dev)
+        nb = 2 * size * size + 4 * size + 8 * size
+        fb = 4 * size * size + 4 * size + 8 * size
         for acc_name, acc in (("f32", 0), ("comp", 1), ("f64combine", 2)):
-            def ca(i, acc=acc):
-                assert lib.lift_asum_ex(n, code, xs[i].data_ptr(), acc, L.LIFT_F64, res.data_ptr(), wsp, wsb,
-                                        None, sh) == 0
-
-            def cd(i, acc=acc):
-                assert lib.lift_dot_ex(n, code, xs[i].data_ptr(), ys[i].data_ptr(), acc, L.LIFT_F64,
-                                       res.data_ptr(), wsp, wsb, None, sh) == 0
-            rec(f"asum_{storage}_{acc_name}_2^26", _time_calls(ca, ns, stream), 2 * n, 4 * n)
-            rec(f"dot_{storage}_{acc_name}_2^26", _time_calls(cd, ns, stream), 4 * n, 8 * n)
-        del xs, ys
-        torch.cuda.empty_cache()
-
-    # batched form (4096 reductions + 256 gemv) vs the same problems per call
-    for storage in ("f32", "bf16"):
-        out.update(batch_form(L, W, dev, stream, storage))
-        torch.cuda.empty_cache()
-
-    # bf16 gemv 16384^2 (A 512 MiB: larger than the Infinity Cache by itself)
-    A, x, y, alpha, beta = W.half_gemv()
-    size = A.shape[0]
-    Ad, xd, yd = A.to(dev), x.to(dev), y.to(dev)
-    nb = 2 * size * size + 4 * size + 8 * size
-    fb = 4 * size * size + 4 * size + 8 * size
-    for acc_name, acc in (("f32", 0), ("comp", 1), ("f64combine", 2)):
-        def cg(i, acc=acc):
-            assert lib.lift_gemv_ex(size, size, alpha, L.LIFT_BF16, Ad.data_ptr(), size, xd.data_ptr(), beta,
-                                    yd.data_ptr(), acc, None, sh) == 0
-        rec(f"gemv_bf16_{acc_name}_{size}", _time_calls(cg, 1, stream, reps=20), nb, fb)
+            def cg(i, acc=acc):
+                assert lib.lift_gemv_ex(size, size, alpha, L.LIFT_BF16, Ad.data_ptr(), size, xd.data_ptr(), beta,
+                                        yd.data_ptr(), acc, None, sh) == 0
+            rec(f"gemv_bf16_{acc_name}_{size}", _time_calls(cg, 1, stream, reps=20), nb, fb)
     return out
 
 
 def batch_form(L, W, dev, stream, storage):
-    """Config-5 batch: one persistent launch vs per-call kernels (eager and
+    """The batch of 4096 reductions + 256 gemv: one persistent launch vs per-call kernels (eager and
     captured in a graph) over the same problems.  Values are drawn on the GPU
     (throughput only; parity is checked by the tests)."""
     import torch

@@ -179,6 +179,30 @@ lift_status lift_gemv_ex(int64_t m, int64_t n, float alpha, lift_dtype at, const
                          int64_t lda, const float *x, float beta, float *y, lift_acc acc,
                          const lift_knobs *knobs, hipStream_t stream);
 
+/* ---- BlackScholes (Section 5.2) ----------------------------------------- */
+
+/* BlackScholes: map(BSComputation) over n stock prices s[i] (binary32, > 0).
+ * For each price the pair {call, put} of the closed-form model of a European
+ * option with the given strike (> 0), risk-free rate, volatility (> 0) and
+ * time to expiry in years (> 0), the same for every element:
+ *   d1 = (ln(s/K) + (r + v^2/2) T) / (v sqrt T),   d2 = d1 - v sqrt T,
+ *   call = s N(d1) - K e^{-rT} N(d2),   put = K e^{-rT} N(-d2) - s N(-d1),
+ * N the standard normal distribution function.  call_put[2i] is the call and
+ * call_put[2i + 1] the put of s[i] (2n floats, 8-byte aligned, not
+ * overlapping s).  Evaluated in binary32: the per-call constants in binary64,
+ * rounded once; ln s from the hardware log2; N through a fitted polynomial
+ * for the normal tail (absolute error about 2e-7).  Prices must be positive
+ * normal binary32 numbers.  LIFT_EINVAL: n < 0, null or misaligned pointers
+ * with n > 0, overlap, or a parameter out of its range or not finite. */
+lift_status lift_blackscholes(int64_t n, const float *s, float strike, float rate, float volatility,
+                              float years, float *call_put, hipStream_t stream);
+
+/* lift_blackscholes with explicit knobs (block, vec_bytes 4/8/16 prices
+ * per lane, unroll, split, wg_per_cu; NULL = defaults). */
+lift_status lift_blackscholes_ex(int64_t n, const float *s, float strike, float rate, float volatility,
+                                 float years, float *call_put, const lift_knobs *knobs,
+                                 hipStream_t stream);
+
 /* ---- batched form ------------------------------------------------------ */
 
 /* Many asum / dot / gemv problems of uneven size in ONE kernel launch.

@@ -1,7 +1,8 @@
 """MI355X-native map/reduce BLAS hot path of arXiv 1502.02389.
 
-scal, asum, dot and gemv as hand-written gfx950 HIP kernels behind the C ABI
-declared in ``include/lift.h``; ``lift`` is the ctypes binding.
+scal, asum, dot and gemv (and BlackScholes, a map over stock prices) as
+hand-written gfx950 HIP kernels behind the C ABI declared in
+``include/lift.h``; ``lift`` is the ctypes binding.
 """
 from .lift import (  # noqa: F401
     ACC, LIFT_ACC_F32, LIFT_ACC_F32_COMP, LIFT_ACC_F32_F64COMBINE, LIFT_BF16, LIFT_EHIP,
@@ -11,4 +12,5 @@ from .lift import (  # noqa: F401
     lift_scal_ex, lift_status_string, lift_time_next_launch, lift_version, lift_workspace_bytes, scal,
     workspace, HipEvents, Batch, GraphRun, lift_problem, lift_batch_create, lift_batch_run,
     lift_batch_capture, lift_batch_info, lift_batch_destroy, LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV,
+    blackscholes, lift_blackscholes, lift_blackscholes_ex,
 )

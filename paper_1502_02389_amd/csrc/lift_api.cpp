@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdint>
 #include <cstring>
@@ -178,6 +179,7 @@ constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0, 32, 1};
 constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1, 1};
 constexpr Knobs DEF_GEMV = {256, 16, 8, 1, 0, 0, 0};
 constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1};
+constexpr Knobs DEF_BS = {256, 4, 4, 1, 0, 16, 1};
 
 // Split a range of n elements of `ebytes` bytes at base address p into a
 // scalar head (up to the first vb-aligned address), whole vb-byte vectors,
@@ -740,6 +742,67 @@ lift_status lift_dot_ex(int64_t n, lift_dtype xt, const void *x, const void *y, 
                         const lift_knobs *knobs, hipStream_t stream)
 {
     return reduce_common(OP_DOT, n, xt, x, y, acc, rt, result, ws, ws_bytes, knobs, stream);
+}
+
+lift_status lift_blackscholes_ex(int64_t n, const float *s, float strike, float rate, float volatility,
+                                 float years, float *call_put, const lift_knobs *knobs, hipStream_t stream)
+{
+    if (n < 0)
+        return LIFT_EINVAL;
+    if (n > 0 && (!s || !call_put || !aligned(s, 4) || !aligned(call_put, 8)))
+        return LIFT_EINVAL;
+    if (overlaps(s, n * 4, call_put, n * 8))
+        return LIFT_EINVAL;
+    if (!(strike > 0.f) || !std::isfinite(strike) || !(volatility > 0.f) || !std::isfinite(volatility) ||
+        !(years > 0.f) || !std::isfinite(years) || !std::isfinite(rate))
+        return LIFT_EINVAL;
+    Knobs k;
+    lift_status st = resolve(knobs, DEF_BS, 4, &k);
+    if (st != LIFT_OK)
+        return st;
+    if (k.vec_bytes < 4)
+        return LIFT_EINVAL;
+    if (n == 0)
+        return LIFT_OK;
+    // vector path: prices vb-aligned after the head, and the head's pairs
+    // aligned for the pair stores (2 vb bytes, at most 16 per store)
+    int vb = k.vec_bytes;
+    Split3 sp;
+    split3(s, nullptr, n, 4, vb, &sp);
+    const uintptr_t out_head = reinterpret_cast<uintptr_t>(call_put) + (uintptr_t)sp.head * 8;
+    if (out_head % (uintptr_t)std::min(2 * vb, 16) != 0) {
+        vb = 4;
+        split3(s, nullptr, n, 4, vb, &sp);
+    }
+    const void *kern = blackscholes_kernel_table(vb, k.unroll);
+    if (!kern)
+        return LIFT_EUNSUPPORTED;
+    int cus = 0;
+    st = cu_count(&cus);
+    if (st != LIFT_OK)
+        return st;
+    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, INT32_MAX);
+    BsArgs a;
+    a.s = s;
+    a.call_put = call_put;
+    a.n = n;
+    a.head = sp.head;
+    a.nvec = sp.nvec;
+    a.chunk = chunk;
+    const double K = strike, r = rate, v = volatility, T = years;
+    const double vst = v * std::sqrt(T);
+    a.ln2_over_vst = (float)(std::log(2.0) / vst);
+    a.d1_offset = (float)(((r + 0.5 * v * v) * T - std::log(K)) / vst);
+    a.vol_sqrt_t = (float)vst;
+    a.strike_disc = (float)(K * std::exp(-r * T));
+    const int64_t grid = std::max<int64_t>(1, (sp.nvec + chunk - 1) / chunk);
+    return launch(kern, grid, k.block, &a, stream);
+}
+
+lift_status lift_blackscholes(int64_t n, const float *s, float strike, float rate, float volatility,
+                              float years, float *call_put, hipStream_t stream)
+{
+    return lift_blackscholes_ex(n, s, strike, rate, volatility, years, call_put, nullptr, stream);
 }
 
 lift_status lift_gemv(int64_t m, int64_t n, float alpha, const float *A, int64_t lda,

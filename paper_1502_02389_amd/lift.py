@@ -88,6 +88,8 @@ SIGNATURES = {
     "lift_asum_ex": (_i32, [_i64, _i32, _vp, _i32, _i32, _vp, _vp, _sz, _kp, _vp]),
     "lift_dot_ex": (_i32, [_i64, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _sz, _kp, _vp]),
     "lift_gemv_ex": (_i32, [_i64, _i64, _f32, _i32, _vp, _i64, _vp, _f32, _vp, _i32, _kp, _vp]),
+    "lift_blackscholes": (_i32, [_i64, _vp, _f32, _f32, _f32, _f32, _vp, _vp]),
+    "lift_blackscholes_ex": (_i32, [_i64, _vp, _f32, _f32, _f32, _f32, _vp, _kp, _vp]),
     "lift_status_string": (ctypes.c_char_p, [_i32]),
     "lift_last_hip_error": (_i32, []),
     "lift_version": (ctypes.c_char_p, []),
@@ -170,6 +172,14 @@ def lift_dot_ex(n, xt, x, y, acc, rt, result, ws, ws_bytes, knobs=None, stream=0
 
 def lift_gemv_ex(m, n, alpha, at, A, lda, x, beta, y, acc, knobs=None, stream=0):
     return _lib().lift_gemv_ex(m, n, alpha, at, A, lda, x, beta, y, acc, _kptr(knobs), stream)
+
+
+def lift_blackscholes(n, s, strike, rate, volatility, years, call_put, stream=0):
+    return _lib().lift_blackscholes(n, s, strike, rate, volatility, years, call_put, stream)
+
+
+def lift_blackscholes_ex(n, s, strike, rate, volatility, years, call_put, knobs=None, stream=0):
+    return _lib().lift_blackscholes_ex(n, s, strike, rate, volatility, years, call_put, _kptr(knobs), stream)
 
 
 def lift_status_string(status):
@@ -374,6 +384,25 @@ def dot(x, y, acc="f32", result_dtype=None, knobs=None):
     """sum x_i y_i as a 0-d device tensor."""
     torch = _torch()
     return _reduce("dot", x, y, acc, result_dtype or torch.float32, knobs)
+
+
+def blackscholes(s, strike, rate, volatility, years, out=None, knobs=None):
+    """map(BSComputation) over binary32 stock prices: an (n, 2) tensor of
+    {call, put} per price (``out`` may be given, (n, 2) float32)."""
+    torch = _torch()
+    _check_tensor(s, "s", (torch.float32,))
+    n = s.numel()
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float32, device=s.device)
+    _check_tensor(out, "out", (torch.float32,))
+    if out.numel() != 2 * n:
+        raise ValueError("out must hold two floats per price")
+    st = _stream_handle(s.device)
+    if knobs is None and n > 0:
+        knobs = _tuned("blackscholes", s.dtype, "f32", n)
+    _ok(lift_blackscholes_ex(n, s.data_ptr(), float(strike), float(rate), float(volatility), float(years),
+                             out.data_ptr(), knobs, st), "lift_blackscholes")
+    return out
 
 
 def gemv(alpha, A, x, beta, y, acc="f32", knobs=None, lda=None):

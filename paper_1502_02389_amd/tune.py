@@ -110,6 +110,11 @@ def grid(op: str, storage: str, quick: bool = False):
         for b, u, r, w in itertools.product((128, 256, 512, 1024), (2, 4, 8), (1, 2), (0, 2, 8)):
             yield dict(block=b, vec_bytes=16, unroll=u, rows_per_wave=r, row_split=2, wg_per_cu=w)
         return
+    if op == "blackscholes":
+        blocks = (256, 512) if quick else (128, 256, 512, 1024)
+        for b, v, u, w in itertools.product(blocks, (4, 8, 16), (1, 2, 4), (2, 4, 8, 16, 32)):
+            yield dict(block=b, vec_bytes=v, unroll=u, wg_per_cu=w)
+        return
     blocks = (256, 512) if quick else (128, 256, 512, 1024)
     vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)
     splits = (0, 1 << 15, 1 << 16, 1 << 17, 1 << 18) if quick else \
@@ -191,6 +196,13 @@ class Operands:
             self.x = (torch.rand(n, generator=g) * 2 - 1).to(dev)
             self.y = torch.zeros(m, device=dev)
             self.bytes = per + 4 * n + 8 * m
+        elif op == "blackscholes":
+            self.n = elements
+            self.bytes = 12 * elements                  # a price in, a {call, put} pair out
+            self.sets = max(2, -(-COLD_BYTES // self.bytes))
+            s = (torch.rand(elements, generator=g) * 25 + 5).to(dev)
+            self.x = [s.clone() for _ in range(self.sets)]
+            self.y = [torch.empty((elements, 2), device=dev) for _ in range(self.sets)]
         else:
             self.n = elements
             streams = {"scal": 2, "asum": 1, "dot": 2}[op]
@@ -208,6 +220,9 @@ class Operands:
         s = self.stream
         if self.op == "scal":
             st = B.lift_scal_ex(self.n, 1.5, self.x[i].data_ptr(), self.y[i].data_ptr(), k, s)
+        elif self.op == "blackscholes":
+            st = B.lift_blackscholes_ex(self.n, self.x[i].data_ptr(), 20.0, 0.02, 0.3, 1.0, self.y[i].data_ptr(),
+                                        k, s)
         elif self.op == "asum":
             st = B.lift_asum_ex(self.n, STORAGE_CODE[self.storage], self.x[i].data_ptr(), acc, B.LIFT_F64,
                                 self.res.data_ptr(), self.ws.data_ptr(), self.ws.numel(), k, s)
@@ -280,7 +295,7 @@ def main(argv=None):
     for op in args.ops.split(","):
         for storage in args.storage.split(","):
             for acc in args.acc.split(","):
-                if op == "scal" and (storage != "f32" or acc != "f32"):
+                if op in ("scal", "blackscholes") and (storage != "f32" or acc != "f32"):
                     continue
                 shapes = ([tuple(int(v) for v in s.split("x")) for s in args.gemv.split(",")] if op == "gemv"
                           else [(0,)] if op == "batch" else [(1 << int(s),) for s in args.sizes.split(",")])

@@ -123,6 +123,18 @@ def wsb():
     (lambda: L.lift_gemv(4, 8, 1.0, X, 8, Y, 0.5, X + 16), L.LIFT_EINVAL),     # y inside A
     (lambda: L.lift_gemv(4, 8, 1.0, X, 8, Y, 0.5, Y + 4), L.LIFT_EINVAL),      # y inside x
     (lambda: L.lift_gemv(4, 8, 1.0, X, 8, Y + 2, 0.5, R), L.LIFT_EINVAL),      # x misaligned
+    (lambda: L.lift_blackscholes(-1, X, 20.0, 0.02, 0.3, 1.0, Y), L.LIFT_EINVAL),
+    (lambda: L.lift_blackscholes(8, 0, 20.0, 0.02, 0.3, 1.0, Y), L.LIFT_EINVAL),       # null prices
+    (lambda: L.lift_blackscholes(8, X, 20.0, 0.02, 0.3, 1.0, 0), L.LIFT_EINVAL),       # null output
+    (lambda: L.lift_blackscholes(8, X + 2, 20.0, 0.02, 0.3, 1.0, Y), L.LIFT_EINVAL),   # prices misaligned
+    (lambda: L.lift_blackscholes(8, X, 20.0, 0.02, 0.3, 1.0, Y + 4), L.LIFT_EINVAL),   # pairs not 8-aligned
+    (lambda: L.lift_blackscholes(8, X, 20.0, 0.02, 0.3, 1.0, X + 16), L.LIFT_EINVAL),  # overlap
+    (lambda: L.lift_blackscholes(8, X, 0.0, 0.02, 0.3, 1.0, Y), L.LIFT_EINVAL),        # strike
+    (lambda: L.lift_blackscholes(8, X, 20.0, 0.02, -0.3, 1.0, Y), L.LIFT_EINVAL),      # volatility
+    (lambda: L.lift_blackscholes(8, X, 20.0, 0.02, 0.3, 0.0, Y), L.LIFT_EINVAL),       # expiry
+    (lambda: L.lift_blackscholes(8, X, 20.0, float("nan"), 0.3, 1.0, Y), L.LIFT_EINVAL),  # rate
+    (lambda: L.lift_blackscholes(8, X, float("inf"), 0.02, 0.3, 1.0, Y), L.LIFT_EINVAL),
+    (lambda: L.lift_blackscholes(0, X, 20.0, 0.02, 0.3, 1.0, Y), L.LIFT_OK),           # empty: no-op
 ])
 def test_rejects_before_any_hip_call(case, expect):
     assert case() == expect
@@ -145,6 +157,8 @@ def test_ex_rejects_bad_enums_and_knobs():
     assert L.lift_gemv_ex(4, 8, 1.0, 0, X, 8, Y, 0.5, R, 4) == L.LIFT_EINVAL
     assert L.lift_gemv_ex(4, 8, 1.0, 0, X, 8, Y, 0.5, R, 0, B.knobs(row_split=5)) == L.LIFT_EINVAL
     assert L.lift_scal_ex(8, 1.0, X, Y, B.knobs(unroll=5)) == L.LIFT_EINVAL
+    assert L.lift_blackscholes_ex(8, X, 20.0, 0.02, 0.3, 1.0, Y, B.knobs(vec_bytes=2)) == L.LIFT_EINVAL
+    assert L.lift_blackscholes_ex(8, X, 20.0, 0.02, 0.3, 1.0, Y, B.knobs(block=100)) == L.LIFT_EINVAL
 
 
 @cpu_only
