@@ -21,7 +21,7 @@ Also reported on the same JSON line:
                  split-join form on the host cores (value) and sequentially on
                  one thread; each timed for a bounded number of seconds
   kernels      : per-kernel average durations from back-to-back launches
-  forms        : BlackScholes over 2^22 prices, gemv fp32 (4096^2, 8192^2,
+  forms        : BlackScholes over 2^22 prices, MD (12288 and 2^20 particles), gemv fp32 (4096^2, 8192^2,
                  16384^2), 16-bit storage (n = 2^26 asum/dot,
                  bf16 gemv 16384^2) in each accumulation variant, as GB/s and
                  binary32-equivalent GB/s
@@ -45,7 +45,7 @@ sys.path.insert(0, ROOT)
 PEAK_GBS = 8000.0
 METRIC = "HBM GB/s and % of 8 TB/s peak: asum/dot/gemv FP32 vs BF16 and batched forms"
 COLD_BYTES = 1 << 30          # rotate buffer sets until at least this much is touched
-FORMS = ("gemv", "half", "batch", "blackscholes", "gemv16")
+FORMS = ("gemv", "half", "batch", "blackscholes", "md", "gemv16")
 
 
 def log(*a):
@@ -373,6 +373,30 @@ def forms(L, W, dev, stream, which=FORMS):
         del ss, outs
         torch.cuda.empty_cache()
 
+    if "md" in which:
+        # MD: 12288 particles (the paper's size) and 2^20, 128 neighbour slots
+        # each, particles in random order (irregular gathers); 2^20 also in
+        # lattice order, as after a spatial sort of the particles
+        for box, tag, shuffle in ((W.MD_BOX, "12288", True), (W.MD_BOX_LARGE, "2^20", True),
+                                  (W.MD_BOX_LARGE, "2^20_sorted", False)):
+            pos, nbr, params = W.md_system(box, shuffle=shuffle)
+            n, k = nbr.shape
+            nb = n * k * 4 + 2 * 16 * n
+            pairs = out_pairs(pos, nbr, params[0], dev)
+            ns = max(2, -(-COLD_BYTES // nb))
+            ps = [pos.to(dev) for _ in range(ns)]
+            nbs = [nbr.to(dev) for _ in range(ns)]
+            fs = [torch.empty((n, 4), device=dev) for _ in range(ns)]
+
+            def cm(i, ps=ps, nbs=nbs, fs=fs, n=n, k=k, params=params):
+                assert lib.lift_md(n, ps[i].data_ptr(), k, nbs[i].data_ptr(), *params, fs[i].data_ptr(), sh) == 0
+            name = f"md_f32_{tag}_particles"
+            rec(name, _time_calls(cm, ns, stream), nb, nb)
+            out[name]["interactions_per_s"] = round(pairs / (out[name]["avg_us"] * 1e-6), 1)
+            out[name]["slots_per_particle"] = k
+            del ps, nbs, fs
+            torch.cuda.empty_cache()
+
     if "gemv16" in which:
         # bf16 gemv 16384^2 (A 512 MiB: larger than the Infinity Cache by itself)
         A, x, y, alpha, beta = W.half_gemv()
@@ -386,6 +410,27 @@ def forms(L, W, dev, stream, which=FORMS):
                                         yd.data_ptr(), acc, None, sh) == 0
             rec(f"gemv_bf16_{acc_name}_{size}", _time_calls(cg, 1, stream, reps=20), nb, fb)
     return out
+
+
+def out_pairs(pos, nbr, cutoff, dev):
+    """Interacting (particle, neighbour) pairs: listed, valid, within the cutoff
+    (binary32 squared distance against binary32(cutoff^2)), for the
+    interactions-per-second figure; counted with torch on the device."""
+    import numpy as np
+    import torch
+
+    p = pos.to(dev)
+    n = p.shape[0]
+    t2 = float(np.float32(float(cutoff) * float(cutoff)))
+    total = 0
+    for lo in range(0, n, 1 << 16):
+        idx = nbr[lo:lo + (1 << 16)].to(dev).long()
+        ok = (idx >= 0) & (idx < n)
+        q = p[idx.clamp(0, n - 1)]
+        d = p[lo:lo + (1 << 16), None, :3] - q[..., :3]
+        r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+        total += int((ok & (r2 < t2)).sum().item())
+    return total
 
 
 def batch_form(L, W, dev, stream, storage):

@@ -124,6 +124,9 @@ typedef struct lift_knobs {
                               choice (2, with a work-group of up to 512
                               threads sized to the row, where x fits in
                               registers; else 1) */
+    int32_t lanes_per_item; /* MD only: lanes that share one particle's
+                              neighbour list: 1, 2, 4, 8 or 16 */
+    int32_t reserved;      /* must be 0 */
 } lift_knobs;
 
 /* ---- plain FP32 forms (Fig. 5) --------------------------------------- */
@@ -202,6 +205,34 @@ lift_status lift_blackscholes(int64_t n, const float *s, float strike, float rat
 lift_status lift_blackscholes_ex(int64_t n, const float *s, float strike, float rate, float volatility,
                                  float years, float *call_put, const lift_knobs *knobs,
                                  hipStream_t stream);
+
+/* ---- MD (Fig. 7) ------------------------------------------------------- */
+
+/* MD: the force on every particle from its neighbour list,
+ *   md(ps, N, t) = map(lambda (p, ns): reduce(lambda (f, nId):
+ *                      updateF(f, nId, p, ps, t), 0, ns)) . zip(ps, N),
+ * where updateF adds the pair force of ps[nId] on p when |p - ps[nId]| < t.
+ * The pair force (not given in the paper) is Lennard-Jones:
+ *   F = 24 eps / r^2 * (2 (sigma^2/r^2)^6 - (sigma^2/r^2)^3) * (p - q).
+ * pos:   n particles, 4 floats each (x, y, z, unused), 16-byte aligned.
+ * nbr:   n x k int32, row-major (nbr[i*k + j] = j-th neighbour of i); an index
+ *        outside [0, n) is an empty slot (lists of uneven length are padded,
+ *        e.g. with -1).  A particle must not list itself.
+ * force: n x 4 floats (fx, fy, fz, 0), 16-byte aligned, not overlapping pos
+ *        or nbr.
+ * cutoff >= 0 (the test is r^2 < binary32(cutoff^2), taken in binary32 on
+ * ((dx dx + dy dy) + dz dz)), epsilon finite, sigma > 0.  Binary32 throughout;
+ * the sum over a list is split over the lanes given by lanes_per_item, in a
+ * fixed order (deterministic).  LIFT_EINVAL for bad sizes, pointers or
+ * parameters; n must be below 2^31. */
+lift_status lift_md(int64_t n, const float *pos, int64_t k, const int32_t *nbr, float cutoff, float epsilon,
+                    float sigma, float *force, hipStream_t stream);
+
+/* lift_md with explicit knobs (block, vec_bytes 4/8/16 = indices per load,
+ * unroll 1/2/4, lanes_per_item; NULL = defaults). */
+lift_status lift_md_ex(int64_t n, const float *pos, int64_t k, const int32_t *nbr, float cutoff,
+                       float epsilon, float sigma, float *force, const lift_knobs *knobs,
+                       hipStream_t stream);
 
 /* ---- batched form ------------------------------------------------------ */
 

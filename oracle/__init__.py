@@ -10,8 +10,9 @@ Two independent implementations of the same definitions live here:
 * ``lift_oracle.c`` (built with gcc into ``liboracle.so``): scal, asum, dot
   and gemv as the literal compositions of the paper's BLAS figure (Fig. 5),
   evaluated in binary64 with a sequential left fold for ``reduce`` -- the
-  full-size numeric oracle -- and BlackScholes as map(BSComputation) over
-  stock prices (Section 5.2, closed-form model);
+  full-size numeric oracle -- BlackScholes as map(BSComputation) over
+  stock prices (Section 5.2, closed-form model), and MD as a map over
+  particles of a reduce over neighbour indices (Fig. 7, Lennard-Jones);
 * ``patterns.py``: the paper's patterns (Tables 1 and 2) as Python functions,
   used for the rewrite-rule, derivation and low-level-expression pins.
 
@@ -72,9 +73,10 @@ def _configure(lib):
     lib.oracle_asum_par.argtypes = [i64, i32, vp, dp, i32]
     lib.oracle_dot_par.argtypes = [i64, i32, vp, i32, vp, dp, i32]
     lib.oracle_blackscholes.argtypes = [i64, i32, vp, dbl, dbl, dbl, dbl, dp]
+    lib.oracle_md.argtypes = [i64, vp, i64, vp, dbl, dbl, dbl, dp, dp]
     for name in ("oracle_widen", "oracle_scal", "oracle_asum", "oracle_dot",
                  "oracle_dot_absmass", "oracle_gemv", "oracle_gemv_absmass",
-                 "oracle_scal_par", "oracle_asum_par", "oracle_dot_par", "oracle_blackscholes"):
+                 "oracle_scal_par", "oracle_asum_par", "oracle_dot_par", "oracle_blackscholes", "oracle_md"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -253,3 +255,24 @@ def blackscholes(s: np.ndarray, strike: float, rate: float, volatility: float, y
                                        float(volatility), float(years),
                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "blackscholes")
     return out
+
+
+# ---------------------------------------------------------------- MD
+def md(pos: np.ndarray, nbr: np.ndarray, cutoff: float, epsilon: float, sigma: float, with_mass: bool = False):
+    """Forces on n particles: pos (n, 4) float32 (x, y, z, unused), nbr
+    (n, k) int32 neighbour indices (outside [0, n) = empty slot).  Returns
+    (n, 3) binary64 forces, and with ``with_mass`` also sum |terms| per
+    component (the scale of rounding error)."""
+    pos = _flat(pos)
+    nbr = _flat(nbr)
+    if pos.dtype != np.float32 or pos.ndim != 2 or pos.shape[1] != 4:
+        raise TypeError("pos must be (n, 4) float32")
+    if nbr.dtype != np.int32 or nbr.ndim != 2 or nbr.shape[0] != pos.shape[0]:
+        raise TypeError("nbr must be (n, k) int32")
+    n, k = pos.shape[0], nbr.shape[1]
+    f = np.empty((n, 3), dtype=np.float64)
+    m = np.empty((n, 3), dtype=np.float64) if with_mass else None
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(_load().oracle_md(n, _ptr(pos), k, _ptr(nbr), float(cutoff), float(epsilon), float(sigma),
+                             f.ctypes.data_as(dp), m.ctypes.data_as(dp) if with_mass else None), "md")
+    return (f, m) if with_mass else f

@@ -528,3 +528,97 @@ int oracle_blackscholes(int64_t n, int st, const void *s, double strike, double 
     free(w);
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* MD: map over particles of a reduce over neighbour indices (Fig. 7)  */
+/* ------------------------------------------------------------------ */
+/*
+ *   md(ps, N, t) = map(lambda (p, ns): reduce(lambda (f, nId):
+ *                         updateF(f, nId, p, ps, t), 0, ns)) . zip(ps, N)
+ *   updateF(f, nId, p, ps, t): q = ps[nId]; d = distance(p, q);
+ *                              if d < t then f + calculateForce(p, q) else f
+ *
+ * The paper gives neither calculateForce nor the neighbour lists.  Readings:
+ *   - the force of q on p is the Lennard-Jones pair force
+ *       F = 24 eps / r^2 * (2 (sigma^2/r^2)^6 - (sigma^2/r^2)^3) * (p - q),
+ *     r = |p - q|, i.e. minus the gradient of 4 eps ((sigma/r)^12 - (sigma/r)^6);
+ *   - positions are 4 floats per particle (x, y, z, unused), forces 3 values;
+ *   - N is an n x k row-major matrix of int32 indices; an index outside
+ *     [0, n) is an empty slot and leaves f unchanged (lists of uneven length);
+ *   - "d < t" is taken as r^2 < t^2, and this decision (an integer outcome
+ *     decided by floating point) is taken in binary32 exactly as the GPU
+ *     kernel takes it: differences and ((dx dx + dy dy) + dz dz) in binary32
+ *     without contraction, compared with t2 = binary32(t * t).  The force is
+ *     then evaluated in binary64 from the stored binary32 positions;
+ *   - reduce is the sequential fold over the list in order (the fused lambda
+ *     is valid only for reduce-seq).
+ */
+typedef struct { double x, y, z; } vec3_t;
+typedef struct { double eps24, sigma2; float t2; } md_params;
+
+static int md_within(const float *p, const float *q, float t2)
+{
+    volatile float dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+    volatile float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    volatile float r2 = (xx + yy) + zz;
+    return r2 < t2;
+}
+
+/* calculateForce: the pair force on p from q (binary64 from binary32 input) */
+static vec3_t calculate_force(const float *p, const float *q, const md_params *m, vec3_t *mass)
+{
+    double dx = (double)p[0] - q[0], dy = (double)p[1] - q[1], dz = (double)p[2] - q[2];
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double s2 = m->sigma2 / r2;
+    double s6 = s2 * s2 * s2;
+    double a = m->eps24 / r2 * s6 * 2.0 * s6;  /* repulsive term */
+    double b = m->eps24 / r2 * s6;             /* attractive term */
+    vec3_t f = {(a - b) * dx, (a - b) * dy, (a - b) * dz};
+    if (mass) {  /* |terms|: the scale of the rounding error of f */
+        mass->x += (a + b) * fabs(dx);
+        mass->y += (a + b) * fabs(dy);
+        mass->z += (a + b) * fabs(dz);
+    }
+    return f;
+}
+
+static vec3_t update_f(vec3_t f, int32_t nid, const float *p, const float *ps, int64_t n, const md_params *m,
+                       vec3_t *mass)
+{
+    if (nid < 0 || (int64_t)nid >= n)
+        return f;  /* empty slot */
+    const float *q = ps + 4 * (int64_t)nid;
+    if (md_within(p, q, m->t2)) {
+        vec3_t g = calculate_force(p, q, m, mass);
+        f.x += g.x;
+        f.y += g.y;
+        f.z += g.z;
+    }
+    return f;
+}
+
+int oracle_md(int64_t n, const float *pos, int64_t k, const int32_t *nbr, double cutoff, double epsilon,
+              double sigma, double *force, double *mass)
+{
+    if (n < 0 || k < 0 || (n > 0 && (!pos || !force)) || (n > 0 && k > 0 && !nbr))
+        return OR_EINVAL;
+    if (!(cutoff >= 0) || !isfinite(cutoff) || !(sigma > 0) || !isfinite(sigma) || !isfinite(epsilon))
+        return OR_EINVAL;
+    md_params m = {24.0 * epsilon, sigma * sigma, (float)(cutoff * cutoff)};
+    for (int64_t i = 0; i < n; ++i) {  /* map over zip(ps, N) */
+        const float *p = pos + 4 * i;
+        vec3_t f = {0.0, 0.0, 0.0};    /* reduce(..., 0, ns): fold in list order */
+        vec3_t ms = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < k; ++j)
+            f = update_f(f, nbr[i * k + j], p, pos, n, &m, mass ? &ms : NULL);
+        force[3 * i] = f.x;
+        force[3 * i + 1] = f.y;
+        force[3 * i + 2] = f.z;
+        if (mass) {
+            mass[3 * i] = ms.x;
+            mass[3 * i + 1] = ms.y;
+            mass[3 * i + 2] = ms.z;
+        }
+    }
+    return OR_OK;
+}

@@ -1,7 +1,8 @@
 """MI355X-native map/reduce BLAS hot path of arXiv 1502.02389.
 
-scal, asum, dot and gemv (and BlackScholes, a map over stock prices) as
-hand-written gfx950 HIP kernels behind the C ABI declared in
+scal, asum, dot and gemv (and BlackScholes, a map over stock prices, and MD,
+a map over particles of a reduce over neighbour lists) as hand-written gfx950
+HIP kernels behind the C ABI declared in
 ``include/lift.h``; ``lift`` is the ctypes binding.
 """
 from .lift import (  # noqa: F401
@@ -12,5 +13,5 @@ from .lift import (  # noqa: F401
     lift_scal_ex, lift_status_string, lift_time_next_launch, lift_version, lift_workspace_bytes, scal,
     workspace, HipEvents, Batch, GraphRun, lift_problem, lift_batch_create, lift_batch_run,
     lift_batch_capture, lift_batch_info, lift_batch_destroy, LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV,
-    blackscholes, lift_blackscholes, lift_blackscholes_ex,
+    blackscholes, lift_blackscholes, lift_blackscholes_ex, md, lift_md, lift_md_ex,
 )

@@ -130,6 +130,7 @@ struct Knobs {
     int64_t split;
     int wg_per_cu;
     int row_split;  // 1: wavefront per row group, 2: work-group per row
+    int lanes;      // MD: lanes per particle
 };
 
 // Checks the caller's knobs (0 = default) and merges them with defaults.
@@ -168,6 +169,13 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
         out->wg_per_cu = k->wg_per_cu;
     if (k->row_split)
         out->row_split = k->row_split;
+    if (k->lanes_per_item) {
+        if (!pow2_in(k->lanes_per_item, 1, 16))
+            return LIFT_EINVAL;
+        out->lanes = k->lanes_per_item;
+    }
+    if (k->reserved)
+        return LIFT_EINVAL;
     return LIFT_OK;
 }
 
@@ -175,11 +183,12 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
 // one long-lived work-group per CU (fewer partials, shorter combine tail),
 // scal many one-step work-groups, gemv a work-group per row with x held in
 // registers where one step covers a row (row_split 0 = chosen per shape).
-constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0, 32, 1};
-constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1, 1};
-constexpr Knobs DEF_GEMV = {256, 16, 8, 1, 0, 0, 0};
-constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1};
-constexpr Knobs DEF_BS = {256, 4, 4, 1, 0, 16, 1};
+constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0, 32, 1, 1};
+constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1, 1, 1};
+constexpr Knobs DEF_GEMV = {256, 16, 8, 1, 0, 0, 0, 1};
+constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1, 1};
+constexpr Knobs DEF_BS = {256, 4, 4, 1, 0, 16, 1, 1};
+constexpr Knobs DEF_MD = {256, 16, 2, 1, 0, 0, 1, 16};
 
 // Split a range of n elements of `ebytes` bytes at base address p into a
 // scalar head (up to the first vb-aligned address), whole vb-byte vectors,
@@ -803,6 +812,58 @@ lift_status lift_blackscholes(int64_t n, const float *s, float strike, float rat
                               float years, float *call_put, hipStream_t stream)
 {
     return lift_blackscholes_ex(n, s, strike, rate, volatility, years, call_put, nullptr, stream);
+}
+
+lift_status lift_md_ex(int64_t n, const float *pos, int64_t k, const int32_t *nbr, float cutoff,
+                       float epsilon, float sigma, float *force, const lift_knobs *knobs,
+                       hipStream_t stream)
+{
+    if (n < 0 || k < 0 || n > INT32_MAX)
+        return LIFT_EINVAL;
+    if (n > 0 && (!pos || !force || !aligned(pos, 16) || !aligned(force, 16)))
+        return LIFT_EINVAL;
+    if (n > 0 && k > 0 && (!nbr || !aligned(nbr, 4)))
+        return LIFT_EINVAL;
+    if (n > 0 && k > INT64_MAX / 4 / n)
+        return LIFT_EINVAL;
+    if (overlaps(force, n * 16, pos, n * 16) || overlaps(force, n * 16, nbr, n > 0 ? n * k * 4 : 0))
+        return LIFT_EINVAL;
+    if (!(cutoff >= 0.f) || !std::isfinite(cutoff) || !(sigma > 0.f) || !std::isfinite(sigma) ||
+        !std::isfinite(epsilon))
+        return LIFT_EINVAL;
+    Knobs kn;
+    lift_status st = resolve(knobs, DEF_MD, 4, &kn);
+    if (st != LIFT_OK)
+        return st;
+    if (kn.vec_bytes < 4 || kn.unroll > 4)
+        return LIFT_EINVAL;
+    if (n == 0)
+        return LIFT_OK;
+    // V indices per load when every row starts V-aligned
+    int v = kn.vec_bytes / 4;
+    while (v > 1 && (k % v != 0 || !aligned(nbr, (size_t)v * 4)))
+        v /= 2;
+    const void *kern = md_kernel_table(kn.lanes, v, kn.unroll);
+    if (!kern)
+        return LIFT_EUNSUPPORTED;
+    MdArgs a;
+    a.pos = pos;
+    a.nbr = nbr;
+    a.force = force;
+    a.n = n;
+    a.k = k;
+    a.t2 = (float)((double)cutoff * (double)cutoff);
+    a.sigma2 = (float)((double)sigma * (double)sigma);
+    a.eps24 = (float)(24.0 * (double)epsilon);
+    const int64_t threads = n * kn.lanes;
+    const int64_t grid = (threads + kn.block - 1) / kn.block;
+    return launch(kern, grid, kn.block, &a, stream);
+}
+
+lift_status lift_md(int64_t n, const float *pos, int64_t k, const int32_t *nbr, float cutoff, float epsilon,
+                    float sigma, float *force, hipStream_t stream)
+{
+    return lift_md_ex(n, pos, k, nbr, cutoff, epsilon, sigma, force, nullptr, stream);
 }
 
 lift_status lift_gemv(int64_t m, int64_t n, float alpha, const float *A, int64_t lda,

@@ -66,6 +66,18 @@ struct BsArgs {
     float strike_disc;    // K exp(-r T)
 };
 
+// MD forces: n particles (4 floats each), n x k neighbour indices.
+struct MdArgs {
+    const float *pos;
+    const int32_t *nbr;
+    float *force;
+    int64_t n;
+    int64_t k;
+    float t2;      // binary32(cutoff^2)
+    float sigma2;  // sigma^2
+    float eps24;   // 24 epsilon
+};
+
 // y = alpha * A x + beta * y; rows are handled R at a time by one wavefront;
 // each row has nvec aligned vectors followed by n - nvec * E scalar columns.
 struct GemvArgs {
@@ -148,6 +160,7 @@ const void *gemv_kernel_f32(int acc, int vec_bytes, int rows, int unroll);
 const void *gemv_kernel_bf16(int acc, int vec_bytes, int rows, int unroll);
 const void *gemv_kernel_f16(int acc, int vec_bytes, int rows, int unroll);
 const void *blackscholes_kernel_table(int vec_bytes, int unroll);
+const void *md_kernel_table(int lanes, int v, int unroll);
 const void *gemv_split_kernel_f32(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);
 const void *gemv_split_kernel_bf16(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);
 const void *gemv_split_kernel_f16(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);

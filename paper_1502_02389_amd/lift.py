@@ -46,11 +46,13 @@ class lift_knobs(ctypes.Structure):
         ("split", ctypes.c_int64),
         ("wg_per_cu", ctypes.c_int32),
         ("row_split", ctypes.c_int32),
+        ("lanes_per_item", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
-def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0, wg_per_cu=0, row_split=0):
-    return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split, wg_per_cu, row_split)
+def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0, wg_per_cu=0, row_split=0, lanes_per_item=0):
+    return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split, wg_per_cu, row_split, lanes_per_item, 0)
 
 
 LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV = 0, 1, 2
@@ -90,6 +92,8 @@ SIGNATURES = {
     "lift_gemv_ex": (_i32, [_i64, _i64, _f32, _i32, _vp, _i64, _vp, _f32, _vp, _i32, _kp, _vp]),
     "lift_blackscholes": (_i32, [_i64, _vp, _f32, _f32, _f32, _f32, _vp, _vp]),
     "lift_blackscholes_ex": (_i32, [_i64, _vp, _f32, _f32, _f32, _f32, _vp, _kp, _vp]),
+    "lift_md": (_i32, [_i64, _vp, _i64, _vp, _f32, _f32, _f32, _vp, _vp]),
+    "lift_md_ex": (_i32, [_i64, _vp, _i64, _vp, _f32, _f32, _f32, _vp, _kp, _vp]),
     "lift_status_string": (ctypes.c_char_p, [_i32]),
     "lift_last_hip_error": (_i32, []),
     "lift_version": (ctypes.c_char_p, []),
@@ -180,6 +184,14 @@ def lift_blackscholes(n, s, strike, rate, volatility, years, call_put, stream=0)
 
 def lift_blackscholes_ex(n, s, strike, rate, volatility, years, call_put, knobs=None, stream=0):
     return _lib().lift_blackscholes_ex(n, s, strike, rate, volatility, years, call_put, _kptr(knobs), stream)
+
+
+def lift_md(n, pos, k, nbr, cutoff, epsilon, sigma, force, stream=0):
+    return _lib().lift_md(n, pos, k, nbr, cutoff, epsilon, sigma, force, stream)
+
+
+def lift_md_ex(n, pos, k, nbr, cutoff, epsilon, sigma, force, knobs=None, stream=0):
+    return _lib().lift_md_ex(n, pos, k, nbr, cutoff, epsilon, sigma, force, _kptr(knobs), stream)
 
 
 def lift_status_string(status):
@@ -402,6 +414,31 @@ def blackscholes(s, strike, rate, volatility, years, out=None, knobs=None):
         knobs = _tuned("blackscholes", s.dtype, "f32", n)
     _ok(lift_blackscholes_ex(n, s.data_ptr(), float(strike), float(rate), float(volatility), float(years),
                              out.data_ptr(), knobs, st), "lift_blackscholes")
+    return out
+
+
+def md(pos, nbr, cutoff, epsilon, sigma, out=None, knobs=None):
+    """Forces on n particles from their neighbour lists: pos (n, 4) float32,
+    nbr (n, k) int32 (outside [0, n) = empty slot); returns (n, 4) float32
+    (fx, fy, fz, 0)."""
+    torch = _torch()
+    _check_tensor(pos, "pos", (torch.float32,))
+    _check_tensor(nbr, "nbr", (torch.int32,))
+    if pos.dim() != 2 or pos.shape[1] != 4:
+        raise ValueError("pos must be (n, 4)")
+    if nbr.dim() != 2 or nbr.shape[0] != pos.shape[0]:
+        raise ValueError("nbr must be (n, k)")
+    n, k = pos.shape[0], nbr.shape[1]
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=pos.device)
+    _check_tensor(out, "out", (torch.float32,))
+    if out.numel() != 4 * n:
+        raise ValueError("out must be (n, 4)")
+    st = _stream_handle(pos.device)
+    if knobs is None and n > 0:
+        knobs = _tuned("md", pos.dtype, "f32", n * k)
+    _ok(lift_md_ex(n, pos.data_ptr(), k, nbr.data_ptr(), float(cutoff), float(epsilon), float(sigma),
+                   out.data_ptr(), knobs, st), "lift_md")
     return out
 
 

@@ -110,6 +110,11 @@ def grid(op: str, storage: str, quick: bool = False):
         for b, u, r, w in itertools.product((128, 256, 512, 1024), (2, 4, 8), (1, 2), (0, 2, 8)):
             yield dict(block=b, vec_bytes=16, unroll=u, rows_per_wave=r, row_split=2, wg_per_cu=w)
         return
+    if op == "md":
+        blocks = (256,) if quick else (64, 256, 1024)
+        for b, v, u, l in itertools.product(blocks, (4, 8, 16), (1, 2, 4), (1, 2, 4, 8, 16)):
+            yield dict(block=b, vec_bytes=v, unroll=u, lanes_per_item=l)
+        return
     if op == "blackscholes":
         blocks = (256, 512) if quick else (128, 256, 512, 1024)
         for b, v, u, w in itertools.product(blocks, (4, 8, 16), (1, 2, 4), (2, 4, 8, 16, 32)):
@@ -196,6 +201,17 @@ class Operands:
             self.x = (torch.rand(n, generator=g) * 2 - 1).to(dev)
             self.y = torch.zeros(m, device=dev)
             self.bytes = per + 4 * n + 8 * m
+        elif op == "md":
+            import workloads as W
+
+            box = W.MD_BOX if elements <= W.MD_SLOTS * 16 * 16 * 48 else W.MD_BOX_LARGE
+            pos, nbr, self.params = W.md_system(box)
+            self.n, self.k = pos.shape[0], nbr.shape[1]
+            self.bytes = self.n * self.k * 4 + 2 * 16 * self.n   # lists, positions once, forces
+            self.sets = max(2, -(-COLD_BYTES // self.bytes))
+            self.x = [pos.to(dev) for _ in range(self.sets)]
+            self.nb = [nbr.to(dev) for _ in range(self.sets)]
+            self.y = [torch.empty((self.n, 4), device=dev) for _ in range(self.sets)]
         elif op == "blackscholes":
             self.n = elements
             self.bytes = 12 * elements                  # a price in, a {call, put} pair out
@@ -220,6 +236,9 @@ class Operands:
         s = self.stream
         if self.op == "scal":
             st = B.lift_scal_ex(self.n, 1.5, self.x[i].data_ptr(), self.y[i].data_ptr(), k, s)
+        elif self.op == "md":
+            st = B.lift_md_ex(self.n, self.x[i].data_ptr(), self.k, self.nb[i].data_ptr(), *self.params,
+                              self.y[i].data_ptr(), k, s)
         elif self.op == "blackscholes":
             st = B.lift_blackscholes_ex(self.n, self.x[i].data_ptr(), 20.0, 0.02, 0.3, 1.0, self.y[i].data_ptr(),
                                         k, s)
@@ -295,7 +314,7 @@ def main(argv=None):
     for op in args.ops.split(","):
         for storage in args.storage.split(","):
             for acc in args.acc.split(","):
-                if op in ("scal", "blackscholes") and (storage != "f32" or acc != "f32"):
+                if op in ("scal", "blackscholes", "md") and (storage != "f32" or acc != "f32"):
                     continue
                 shapes = ([tuple(int(v) for v in s.split("x")) for s in args.gemv.split(",")] if op == "gemv"
                           else [(0,)] if op == "batch" else [(1 << int(s),) for s in args.sizes.split(",")])

@@ -62,9 +62,10 @@ def test_enum_values_match_header():
 
 
 def test_struct_layouts():
-    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, int32 row_split
-    assert ctypes.sizeof(B.lift_knobs) == 32
+    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, row_split, lanes_per_item, reserved
+    assert ctypes.sizeof(B.lift_knobs) == 40
     assert B.lift_knobs.split.offset == 16 and B.lift_knobs.wg_per_cu.offset == 24
+    assert B.lift_knobs.lanes_per_item.offset == 32
     # lift_problem: int32 kind, int32 reserved, int64 m, n, lda, 3 pointers, 2 floats
     assert ctypes.sizeof(B.lift_problem) == 64
     assert B.lift_problem.a.offset == 32 and B.lift_problem.alpha.offset == 56
@@ -135,6 +136,21 @@ def wsb():
     (lambda: L.lift_blackscholes(8, X, 20.0, float("nan"), 0.3, 1.0, Y), L.LIFT_EINVAL),  # rate
     (lambda: L.lift_blackscholes(8, X, float("inf"), 0.02, 0.3, 1.0, Y), L.LIFT_EINVAL),
     (lambda: L.lift_blackscholes(0, X, 20.0, 0.02, 0.3, 1.0, Y), L.LIFT_OK),           # empty: no-op
+    (lambda: L.lift_md(-1, X, 4, Y, 2.5, 1.0, 1.0, R), L.LIFT_EINVAL),
+    (lambda: L.lift_md(8, X, -1, Y, 2.5, 1.0, 1.0, R), L.LIFT_EINVAL),
+    (lambda: L.lift_md(8, 0, 4, Y, 2.5, 1.0, 1.0, R), L.LIFT_EINVAL),                # null positions
+    (lambda: L.lift_md(8, X, 4, 0, 2.5, 1.0, 1.0, R), L.LIFT_EINVAL),                # null lists
+    (lambda: L.lift_md(8, X, 4, Y, 2.5, 1.0, 1.0, 0), L.LIFT_EINVAL),                # null forces
+    (lambda: L.lift_md(8, X + 4, 4, Y, 2.5, 1.0, 1.0, R), L.LIFT_EINVAL),            # pos not 16-aligned
+    (lambda: L.lift_md(8, X, 4, Y + 2, 2.5, 1.0, 1.0, R), L.LIFT_EINVAL),            # lists misaligned
+    (lambda: L.lift_md(8, X, 4, Y, 2.5, 1.0, 1.0, R + 8), L.LIFT_EINVAL),            # forces misaligned
+    (lambda: L.lift_md(8, X, 4, Y, 2.5, 1.0, 1.0, X + 64), L.LIFT_EINVAL),           # forces overlap pos
+    (lambda: L.lift_md(8, X, 4, Y, 2.5, 1.0, 1.0, Y + 64), L.LIFT_EINVAL),           # forces overlap lists
+    (lambda: L.lift_md(8, X, 4, Y, -1.0, 1.0, 1.0, R), L.LIFT_EINVAL),               # cutoff
+    (lambda: L.lift_md(8, X, 4, Y, 2.5, 1.0, 0.0, R), L.LIFT_EINVAL),                # sigma
+    (lambda: L.lift_md(8, X, 4, Y, 2.5, float("inf"), 1.0, R), L.LIFT_EINVAL),       # epsilon
+    (lambda: L.lift_md(1 << 31, X, 4, Y, 2.5, 1.0, 1.0, R), L.LIFT_EINVAL),          # n too large
+    (lambda: L.lift_md(0, X, 4, Y, 2.5, 1.0, 1.0, R), L.LIFT_OK),                    # empty: no-op
 ])
 def test_rejects_before_any_hip_call(case, expect):
     assert case() == expect
@@ -159,6 +175,11 @@ def test_ex_rejects_bad_enums_and_knobs():
     assert L.lift_scal_ex(8, 1.0, X, Y, B.knobs(unroll=5)) == L.LIFT_EINVAL
     assert L.lift_blackscholes_ex(8, X, 20.0, 0.02, 0.3, 1.0, Y, B.knobs(vec_bytes=2)) == L.LIFT_EINVAL
     assert L.lift_blackscholes_ex(8, X, 20.0, 0.02, 0.3, 1.0, Y, B.knobs(block=100)) == L.LIFT_EINVAL
+    for bad in (B.knobs(lanes_per_item=3), B.knobs(lanes_per_item=32), B.knobs(unroll=8), B.knobs(vec_bytes=2)):
+        assert L.lift_md_ex(8, X, 4, Y, 2.5, 1.0, 1.0, R, bad) == L.LIFT_EINVAL
+    bad = B.knobs()
+    bad.reserved = 1
+    assert L.lift_md_ex(8, X, 4, Y, 2.5, 1.0, 1.0, R, bad) == L.LIFT_EINVAL
 
 
 @cpu_only

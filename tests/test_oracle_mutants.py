@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_blackscholes as bs
+from tests import test_oracle_md as md
 from tests import test_oracle_blas as pins
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "lift_oracle.c")).read()
@@ -46,6 +47,11 @@ MUTANTS = {
     "bs_call_undiscounted": ("return s * cnd(d1) - q->K * exp(-q->r * q->T) * cnd(d2);",
                              "return s * cnd(d1) - q->K * cnd(d2);"),
     "bs_cnd_wrong_scale": ("0.5 * erfc(-x / sqrt(2.0))", "0.5 * erfc(-x / 2.0)"),
+    "md_force_sign_x": ("double dx = (double)p[0] - q[0]", "double dx = (double)q[0] - p[0]"),
+    "md_drops_repulsion_factor": ("* s6 * 2.0 * s6;", "* s6 * s6;"),
+    "md_cutoff_not_squared": ("(float)(cutoff * cutoff)", "(float)(cutoff)"),
+    "md_ignores_cutoff": ("if (md_within(p, q, m->t2)) {", "if (1) {"),
+    "md_sigma_not_squared": ("md_params m = {24.0 * epsilon, sigma * sigma,", "md_params m = {24.0 * epsilon, sigma,"),
 }
 
 FAST_PINS = [
@@ -67,6 +73,10 @@ FAST_PINS = [
     bs.test_put_call_parity_and_homogeneity,
     bs.test_at_the_forward_call_equals_put,
     bs.test_matches_numerical_integration_all_cases,
+    md.test_gradient_all_cases,
+    md.test_zero_force_at_potential_minimum,
+    md.test_newton_third_law_on_symmetric_lists,
+    md.test_cutoff_and_empty_slots,
 ]
 
 

@@ -59,6 +59,10 @@ HALF_N = 1 << 26            # 16-bit storage asum/dot
 HALF_GEMV = 16384           # bf16 A, square
 BATCH_NRED, BATCH_NGEMV = 4096, 256
 BS_N = 1 << 22              # BlackScholes: "4 million" stock prices
+MD_BOX = (16, 16, 48)       # MD: 12288 particles
+MD_BOX_LARGE = (128, 128, 64)   # 2^20 particles
+MD_SLOTS = 128              # neighbour slots per particle
+MD_CUTOFF, MD_EPSILON, MD_SIGMA = 2.5, 1.0, 1.0
 BS_STRIKE, BS_RATE, BS_VOLATILITY, BS_YEARS = 20.0, 0.02, 0.30, 1.0
 
 
@@ -150,3 +154,42 @@ def blackscholes_prices(n: int = BS_N, seed: int = 6):
     g = gen(seed)
     s = torch.rand(n, generator=g, dtype=torch.float32) * 25 + 5
     return s, (BS_STRIKE, BS_RATE, BS_VOLATILITY, BS_YEARS)
+
+
+def md_system(box=MD_BOX, slots: int = MD_SLOTS, spacing: float = 1.0, jitter: float = 0.1,
+              rlist: float = 2.8, seed: int = 7, shuffle: bool = True):
+    """Particles on a jittered cubic lattice (box = lattice points per axis,
+    spacing 1, jitter U(-0.1, 0.1) per coordinate) with neighbour lists of
+    every lattice point within rlist (a skin beyond the 2.5 cutoff), nearest
+    first, padded with -1 to `slots`; particles at the faces have shorter
+    lists.  With ``shuffle`` the particle order is a random permutation, so
+    the gathers of neighbour positions are irregular.  Returns positions
+    (n, 4) float32 (x, y, z, 0), neighbour indices (n, slots) int32 and
+    (cutoff, epsilon, sigma)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = box
+    n = nx * ny * nz
+    c = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"), -1).reshape(-1, 3)
+    r = int(math.ceil(rlist / spacing))
+    o = np.stack(np.meshgrid(*[np.arange(-r, r + 1)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    d2 = (o * o).sum(1) * spacing * spacing
+    keep = (d2 > 0) & (d2 <= rlist * rlist)
+    o, d2 = o[keep], d2[keep]
+    o = o[np.lexsort((o[:, 2], o[:, 1], o[:, 0], d2))][:slots]
+    pos = np.zeros((n, 4), np.float32)
+    pos[:, :3] = (c * spacing + rng.uniform(-jitter, jitter, (n, 3))).astype(np.float32)
+    perm = rng.permutation(n).astype(np.int32) if shuffle else np.arange(n, dtype=np.int32)
+    inv = np.empty(n, np.int64)                # perm: new index of old particle i
+    inv[perm] = np.arange(n)
+    cx, cy, cz = (c[inv, a].astype(np.int32) for a in range(3))   # lattice coords in the new order
+    nbr = np.full((n, slots), -1, np.int32)
+    for j, (ox, oy, oz) in enumerate(o):
+        qx, qy, qz = cx + ox, cy + oy, cz + oz
+        ok = (qx >= 0) & (qx < nx) & (qy >= 0) & (qy < ny) & (qz >= 0) & (qz < nz)
+        old = (qx * ny + qy) * nz + qz
+        nbr[:, j] = np.where(ok, perm[np.where(ok, old, 0)], -1)
+    pos = pos[inv]
+    return torch.from_numpy(np.ascontiguousarray(pos)), torch.from_numpy(np.ascontiguousarray(nbr)), \
+        (MD_CUTOFF, MD_EPSILON, MD_SIGMA)
