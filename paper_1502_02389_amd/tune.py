@@ -272,21 +272,40 @@ class Operands:
         return best
 
 
-def tune_one(op, storage, acc, elements=None, m=None, n=None, quick=False, log=None):
-    """Search the grid for one call shape; returns (best entry, all results)."""
+def derived(op: str, storage: str, elements: int):
+    """Knob points of the derivations of asum / dot (rewrite.py): each is the
+    launch of the kernel that executes one derived low-level expression."""
+    from . import rewrite
+
+    return rewrite.derived_knob_points(op, elements, elem_bytes=STORAGE_BYTES[storage])
+
+
+def tune_one(op, storage, acc, elements=None, m=None, n=None, quick=False, log=None, space="grid"):
+    """Search one call shape over the fixed grid or, for asum / dot with
+    space="derived", over the kernels of the derived expressions; returns
+    (best entry, all results)."""
     ops = BatchOperands(storage) if op == "batch" else Operands(op, storage, elements, m, n)
     accc = acc if op == "batch" else B.ACC[acc]
+    if space == "derived":
+        if op not in ("asum", "dot"):
+            raise ValueError("derived search covers asum and dot")
+        points = derived(op, storage, elements)
+    else:
+        points = [(kn, None) for kn in grid(op, storage, quick)]
     results = []
-    for kn in grid(op, storage, quick):
+    for kn, d in points:
         k = B.knobs(**kn)
         us = ops.time_us(accc, k)
         gbs = ops.bytes / (us * 1e-6) / 1e9
-        results.append((us, kn, gbs))
+        results.append((us, kn, gbs, d))
         if log:
             log(f"{op} {storage} {acc} {kn} {us:.2f} us {gbs:.0f} GB/s")
     results.sort(key=lambda r: r[0])
-    us, kn, gbs = results[0]
-    return {"knobs": kn, "us": round(us, 3), "GB_s": round(gbs, 1), "bytes": ops.bytes}, results
+    us, kn, gbs, d = results[0]
+    best = {"knobs": kn, "us": round(us, 3), "GB_s": round(gbs, 1), "bytes": ops.bytes}
+    if d is not None:
+        best["expression"] = str(d.expr)
+    return best, [r[:3] for r in results]
 
 
 def main(argv=None):
@@ -300,6 +319,8 @@ def main(argv=None):
     ap.add_argument("--write", action="store_true", help="merge winners into the cache")
     ap.add_argument("--top", type=int, default=5)
     ap.add_argument("--verbose", action="store_true", help="print every knob point")
+    ap.add_argument("--space", default="grid", choices=("grid", "derived"),
+                    help="grid: fixed knob grid; derived: the kernels of the rewrite derivations (asum, dot)")
     args = ap.parse_args(argv)
 
     import torch
@@ -325,7 +346,7 @@ def main(argv=None):
                         elements = shp[0] * shp[1]
                     else:
                         best, res = tune_one(op, storage, acc, elements=shp[0], quick=args.quick,
-                                             log=log if args.verbose else None)
+                                             log=log if args.verbose else None, space=args.space)
                         elements = shp[0]
                     k = key(op, storage, acc, elements)
                     entries[k] = best

@@ -1,0 +1,153 @@
+"""The rewrite-driven derivations, checked with the oracle's pattern evaluator.
+
+Every expression on every derivation path -- from the high-level program
+through each rule application to the lowered form -- is evaluated on integer
+data with oracle/patterns.py and must equal the sum exactly (the rules are
+semantics-preserving, Section 4).  The launch knobs read from a derivation
+must make the library's documented launch rules cut the input exactly as the
+derived expression does.
+"""
+import random
+
+import numpy as np
+import pytest
+
+from oracle import lowered
+from oracle import patterns as P
+from paper_1502_02389_amd import rewrite as R
+
+
+def to_fn(e):
+    """An executable closure for an expression, built from oracle patterns."""
+    if isinstance(e, R.Fun):
+        return {"add": P.add, "abs": P.abs_, "mult": lambda pr: P.mult(pr[0], pr[1]), "id": P.identity}[e.name]
+    if isinstance(e, R.Fused):
+        acc, elem = to_fn(e.acc), to_fn(e.elem)
+        return lambda a, x: acc(a, elem(x))
+    if isinstance(e, R.Comp):
+        return P.compose(*[to_fn(p) for p in e.parts])
+    if isinstance(e, R.Map):
+        return P.map_(to_fn(e.f))
+    if isinstance(e, (R.Reduce, R.PartRed)):
+        z = P.Vec((e.z,) * e.f.n) if isinstance(e.f, R.Vect) else e.z
+        return P.reduce_(to_fn(e.f), z)        # part-red: one valid partial reduction (to one value)
+    if isinstance(e, R.Split):
+        return P.split(e.n)
+    if isinstance(e, R.Join):
+        return P.join()
+    if isinstance(e, R.Iterate):
+        return P.iterate(e.k, to_fn(e.f))
+    if isinstance(e, R.Reorder):
+        return P.reorder_stride(e.stride) if e.stride else (lambda xs: list(reversed(xs)))
+    if isinstance(e, (R.ToLocal, R.ToGlobal)):
+        return to_fn(e.f)
+    if isinstance(e, R.AsVector):
+        return P.as_vector(e.n)
+    if isinstance(e, R.AsScalar):
+        return P.as_scalar()
+    if isinstance(e, R.Vect):
+        return P.vect(e.n, to_fn(e.f))
+    raise TypeError(type(e))
+
+
+def run(e, data):
+    out = to_fn(e)(data)
+    assert len(out) == 1
+    return out[0]
+
+
+N = 1 << 12
+SPACE = dict(widths=(1, 2, 4), lanes=(1, 4, 8, 16), min_chunk=1 << 6, max_chunk=1 << 10)
+
+
+@pytest.fixture(scope="module")
+def data():
+    rng = random.Random(5)
+    x = [rng.randint(-8, 8) for _ in range(N)]
+    y = [rng.randint(-8, 8) for _ in range(N)]
+    return x, y
+
+
+@pytest.mark.parametrize("op", ["asum", "dot"])
+def test_every_step_of_every_derivation_is_exact(op, data):
+    x, y = data
+    inp = x if op == "asum" else list(zip(x, y))
+    want = sum(abs(v) for v in x) if op == "asum" else sum(a * b for a, b in zip(x, y))
+    ds = R.derive_reduction(op, N, **SPACE)
+    assert len(ds) > 50
+    forms = set()
+    for d in ds:
+        assert run(d.start, inp) == want
+        for name, params, e in d.steps:
+            assert run(e, inp) == want, (name, params, str(e))
+        forms.add(str(d.expr))
+    assert len(forms) == len(ds)          # distinct lowered expressions
+
+
+def test_fig9b_shape_is_derived():
+    # the AMD expression of Fig. 9b: 2048 floats per work-group as 512 float4,
+    # split-2 per lane, 256 lanes behind reorder-stride, iterate-8
+    d = R.derive_one("asum", R.Choice(2048, 4, 2, True, True))
+    assert str(d.expr) == (
+        "reduce-seq(plus, 0) o asScalar o join o map-workgroup("
+        "iterate-8(join o map-local(reduce-seq(vect-4(plus), vect-4(0))) o split-2) o join o "
+        "map-local(reduce-seq(vect-4(absAndPlus), vect-4(0))) o split-2 o reorder-stride-256) o "
+        "split-512 o asVector-4")
+    assert R.kernel_knobs(d) == {"block": 256, "vec_bytes": 16, "split": 2048}
+    # Fig. 9c: one lane per work-group, no reorder -- derived, but not this library's kernel
+    d = R.derive_one("asum", R.Choice(32768, 4, 8192, False, False))
+    assert str(d.expr) == ("reduce-seq(plus, 0) o asScalar o join o map-workgroup(reduce-seq(vect-4(absAndPlus), "
+                           "vect-4(0))) o split-8192 o asVector-4")
+    assert R.kernel_knobs(d) is None
+
+
+def test_fig8_prefix_is_the_papers_derivation():
+    d = R.derive_one("asum", R.Choice(1024, 1, 4, True, True))
+    texts = [str(e) for _, _, e in d.steps[:5]]
+    assert texts == [
+        "reduce(plus, 0) o part-red(plus, 0) o map(abs)",
+        "reduce(plus, 0) o join o map(part-red(plus, 0)) o split-1024 o map(abs)",
+        "reduce(plus, 0) o join o map(part-red(plus, 0)) o split-1024 o join o map(map(abs)) o split-1024",
+        "reduce(plus, 0) o join o map(part-red(plus, 0)) o map(map(abs)) o split-1024",
+        "reduce(plus, 0) o join o map(part-red(plus, 0) o map(abs)) o split-1024",
+    ]
+
+
+@pytest.mark.parametrize("op", ["asum", "dot"])
+def test_knobs_reproduce_the_derived_partition(op):
+    n = 1 << 24
+    pts = R.derived_knob_points(op, n)
+    assert len(pts) > 100
+    for k, d in pts:
+        c = R._choice_of(d)
+        e = k["vec_bytes"] // 4
+        shape = lowered.launch_shape(n, 4, k["vec_bytes"], k["block"], k["unroll"], k["split"])
+        assert shape.e == c.width == e
+        assert shape.block == c.lanes
+        assert shape.chunk == c.chunk // e              # vectors per work-group
+        assert shape.grid == n // c.chunk
+        assert shape.head == 0 and shape.tail == 0
+
+
+def test_rules_check_their_preconditions():
+    with pytest.raises(R.RuleError):
+        R.split_join(R.Map(R.ABS, "seq"), 4)
+    with pytest.raises(R.RuleError):
+        R.reduction(R.Reduce(R.ADD, 0, True))
+    with pytest.raises(R.RuleError):
+        R.simplify_split_join(R.comp(R.Split(4), R.Join(), R.Map(R.Map(R.ABS)), R.Split(8)), 0)
+    with pytest.raises(R.RuleError):
+        R.fuse_maps(R.comp(R.Map(R.ABS, "local"), R.Map(R.ABS, "seq")), 0)
+    with pytest.raises(R.RuleError):
+        R.lower_reorder(R.Reorder(4), 8)
+    with pytest.raises(R.RuleError):
+        R.derive_one("asum", R.Choice(4096, 1, 3, True, True))   # 4096/3 lanes: not a power of two
+
+
+def test_unimplementable_forms_get_no_kernel():
+    n = 1 << 20
+    for d in R.derive_reduction("asum", n):
+        c = R._choice_of(d)
+        k = R.kernel_knobs(d)
+        ok = c.reorder and c.tree and 64 <= c.lanes <= 1024
+        assert (k is not None) == ok
