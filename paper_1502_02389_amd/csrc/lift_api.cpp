@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "lift.h"
+#include "lift_apps.hpp"
 #include "lift_internal.hpp"
 
 using namespace lift;

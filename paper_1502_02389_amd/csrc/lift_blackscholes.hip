@@ -18,6 +18,7 @@
 // U loads in flight, each lane storing its E pairs (2 VB bytes) right after
 // the computation; a scalar head and tail cover any 4-byte-aligned input.
 #include "lift_device.hpp"
+#include "lift_apps.hpp"
 #include "lift_internal.hpp"
 
 namespace lift {

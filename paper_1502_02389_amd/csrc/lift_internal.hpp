@@ -51,33 +51,6 @@ struct ScalArgs {
     float alpha;
 };
 
-// BlackScholes over n prices: head scalars, nvec VB-byte vectors of prices,
-// then the scalar tail; the per-call constants of the model in binary32.
-struct BsArgs {
-    const float *s;
-    float *call_put;      // 2n floats: {call, put} per price
-    int64_t n;
-    int64_t head;
-    int64_t nvec;
-    int64_t chunk;        // vectors per work-group
-    float ln2_over_vst;   // ln 2 / (v sqrt T): d1 = log2(s) ln2_over_vst + d1_offset
-    float d1_offset;      // ((r + v^2 / 2) T - ln K) / (v sqrt T)
-    float vol_sqrt_t;     // v sqrt T
-    float strike_disc;    // K exp(-r T)
-};
-
-// MD forces: n particles (4 floats each), n x k neighbour indices.
-struct MdArgs {
-    const float *pos;
-    const int32_t *nbr;
-    float *force;
-    int64_t n;
-    int64_t k;
-    float t2;      // binary32(cutoff^2)
-    float sigma2;  // sigma^2
-    float eps24;   // 24 epsilon
-};
-
 // y = alpha * A x + beta * y; rows are handled R at a time by one wavefront;
 // each row has nvec aligned vectors followed by n - nvec * E scalar columns.
 struct GemvArgs {
@@ -159,8 +132,6 @@ const void *reduce_kernel_f16(int op, int acc, int vec_bytes, int unroll);
 const void *gemv_kernel_f32(int acc, int vec_bytes, int rows, int unroll);
 const void *gemv_kernel_bf16(int acc, int vec_bytes, int rows, int unroll);
 const void *gemv_kernel_f16(int acc, int vec_bytes, int rows, int unroll);
-const void *blackscholes_kernel_table(int vec_bytes, int unroll);
-const void *md_kernel_table(int lanes, int v, int unroll);
 const void *gemv_split_kernel_f32(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);
 const void *gemv_split_kernel_bf16(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);
 const void *gemv_split_kernel_f16(int acc, int vec_bytes, int rows, int unroll, bool x_stationary);

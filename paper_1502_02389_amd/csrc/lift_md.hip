@@ -20,6 +20,7 @@
 // decision), then 1/r2 by the hardware reciprocal, s6 = (sigma^2 / r2)^3 and
 // F = 24 eps / r2 * s6 * (2 s6 - 1) * d.
 #include "lift_device.hpp"
+#include "lift_apps.hpp"
 #include "lift_internal.hpp"
 
 namespace lift {
