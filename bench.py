@@ -20,7 +20,9 @@ Also reported on the same JSON line:
   cpu_baseline : the binary64 oracle on the same workload and data, in its
                  split-join form on the host cores (value) and sequentially on
                  one thread; each timed for a bounded number of seconds
-  kernels      : per-kernel average durations from back-to-back launches
+  kernels      : per-kernel average durations from back-to-back launches, and
+                 median / p10 / p90 of 200 single launches timed inside their
+                 dispatch, cold (rotating buffer sets) and warm (one set)
   forms        : BlackScholes over 2^22 prices, MD (12288 and 2^20 particles), gemv fp32 (4096^2, 8192^2,
                  16384^2), 16-bit storage (n = 2^26 asum/dot,
                  bf16 gemv 16384^2) in each accumulation variant, as GB/s and
@@ -174,6 +176,13 @@ def main():
         gbs = bytes_kernel[k] / (us * 1e-6) / 1e9
         kernels[k] = {"avg_us": round(us, 3), "bytes": bytes_kernel[k], "GB_s": round(gbs, 1),
                       "frac_of_peak": round(gbs / PEAK_GBS, 4)}
+        # per-launch durations (events inside each dispatch): cold (rotating
+        # sets) and warm (one set, 64-128 MiB that the 256 MB cache can hold)
+        for label, pick in (("cold", lambda i: ptr[i % nsets]), ("warm", lambda i: ptr[0])):
+            d = _per_launch_us(L, lambda i, pick=pick, k=k: launch(k, pick(i)), 200)
+            kernels[k][label] = {"median_us": round(d[len(d) // 2], 3), "p10_us": round(d[len(d) // 10], 3),
+                                 "p90_us": round(d[(9 * len(d)) // 10], 3),
+                                 "median_GB_s": round(bytes_kernel[k] / (d[len(d) // 2] * 1e-6) / 1e9, 1)}
         log("kernel", k, kernels[k])
     # the roofline kernel: dot -- with scal the largest share of the step
     # (the two move the same bytes and time within noise of each other)
@@ -240,11 +249,22 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_cpu, y_cpu, alpha, seconds, gpu_set, step_bytes):
     """The binary64 oracle timed on whole steps of the same workload (scal,
     asum, dot over the same host arrays): first the sequential composition on
     one thread, then its split-join form (rule 3d) on every host core this
-    process may use, each until `seconds` have elapsed (at least one step)."""
+    process may use, each for `seconds` (at least 5 steps); the median step
+    time gives the rate.  Timing includes the exact widening to binary64."""
     import oracle
 
     xs, ys = x_cpu.numpy(), y_cpu.numpy()
@@ -252,12 +272,12 @@ def cpu_baseline(x_cpu, y_cpu, alpha, seconds, gpu_set, step_bytes):
     threads = oracle.host_threads()
 
     def timed(step):
-        reps, t0 = 0, time.perf_counter()
-        while True:
+        times, t_end, res = [], time.perf_counter() + seconds, None
+        while len(times) < 5 or time.perf_counter() < t_end:
+            t0 = time.perf_counter()
             res = step()
-            reps += 1
-            if time.perf_counter() - t0 >= seconds:
-                return reps, time.perf_counter() - t0, res
+            times.append(time.perf_counter() - t0)
+        return sorted(times), res
 
     def seq():
         oracle.scal(alpha, xs)
@@ -267,20 +287,41 @@ def cpu_baseline(x_cpu, y_cpu, alpha, seconds, gpu_set, step_bytes):
         oracle.scal_par(alpha, xs, threads)
         return oracle.asum_par(xs, threads), oracle.dot_par(xs, ys, threads)
 
-    r1, el1, (ra, rd) = timed(seq)
-    rp, elp, _ = timed(par)
-    g1 = step_bytes * r1 / el1 / 1e9
-    gp = step_bytes * rp / elp / 1e9
+    t1, (ra, rd) = timed(seq)
+    tp, _ = timed(par)
+    m1, mp = t1[len(t1) // 2], tp[len(tp) // 2]
+    g1, gp = step_bytes / m1 / 1e9, step_bytes / mp / 1e9
     ga, gd = float(gpu_set["ra"].item()), float(gpu_set["rd"].item())
     mass = oracle.dot_absmass(xs, ys)
-    log("cpu oracle 1 thread:", r1, "steps in", f"{el1:.1f}s", f"{g1:.3f} GB/s;",
-        threads, "threads:", rp, "steps in", f"{elp:.1f}s", f"{gp:.3f} GB/s")
+    log("cpu oracle 1 thread:", len(t1), "steps, median", f"{m1 * 1e3:.1f} ms", f"{g1:.3f} GB/s;",
+        threads, "threads:", len(tp), "steps, median", f"{mp * 1e3:.1f} ms", f"{gp:.3f} GB/s")
     return {"value": round(gp, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rp} full steps (scal+asum+dot, n=2^24, same arrays) of the binary64 C oracle in its "
-                      f"split-join form on {threads} threads, {elp:.1f} s",
+            "sample": f"median of {len(tp)} full steps (scal+asum+dot, n=2^24, same arrays, binary64 widening "
+                      f"included) of the C oracle in its split-join form on {threads} threads, "
+                      f"{sum(tp):.1f} s in all",
+            "cpu_model": _cpu_model(),
             "single_thread": {"value": round(g1, 4), "unit": "GB/s", "cores": 1,
-                              "sample": f"{r1} full steps of the sequential composition, {el1:.1f} s"},
+                              "sample": f"median of {len(t1)} full steps of the sequential composition, "
+                                        f"{sum(t1):.1f} s in all"},
             "gpu_vs_oracle": {"asum_rel_err": abs(ga - ra) / ra, "dot_err_over_absmass": abs(gd - rd) / mass}}
+
+
+def _per_launch_us(L, launch, reps):
+    """Sorted durations of `reps` launches, each timed by HIP events recorded
+    with its own dispatch (launch(i) must make exactly one library launch)."""
+    import torch
+
+    ev = L.HipEvents(2 * reps)
+    try:
+        for i in range(reps):
+            st = L.lift_time_next_launch(ev.events[2 * i], ev.events[2 * i + 1])
+            if st != 0:
+                raise L.LiftError(st, "lift_time_next_launch")
+            launch(i)
+        torch.cuda.synchronize()
+        return sorted(ev.elapsed_ms(2 * i, 2 * i + 1) * 1e3 for i in range(reps))
+    finally:
+        ev.close()
 
 
 def _time_calls(fn, nsets, stream, reps=50, warm=5):
