@@ -9,7 +9,8 @@
 //                     the work-group that finishes a problem's last tile folds
 //                     that problem's partials in tile order and writes its
 //                     result;
-//   gemv tile      -> each wavefront takes rows of the tile (gemv_row_group).
+//   gemv tile      -> each wavefront takes pairs of rows of the tile
+//                     (gemv_row_group).
 // Tile-to-work-group assignment is dynamic, but every tile's arithmetic and
 // every combine order are fixed by the plan, so results are deterministic.
 // The last work-group to leave resets the tile counter, so the launch can be
@@ -95,17 +96,24 @@ __device__ __forceinline__ typename BlockT<ACC>::type tile_lane_value(const Batc
     return acc.value();
 }
 
-// Rows [begin, begin + len) of a gemv problem: wavefront w takes rows
-// begin + w, begin + w + W, ... (W wavefronts per work-group).
+// Rows [begin, begin + len) of a gemv problem, two rows per wavefront at a
+// time so the pair shares every x load (x is re-read from cache for each row
+// group; with 16-bit A that is otherwise twice A's own bytes): wavefront w
+// takes rows begin + 2w, begin + 2w + 2W, ... (W wavefronts per work-group).
+// The tile's end stands in for the row count, so a second row past it is
+// read at a clamped index and never written: no row of another tile is
+// touched.
 template <class T, int ACC, int VB, int U>
 __device__ __forceinline__ void gemv_tile(const BatchProblem &p, const BatchTile &tl)
 {
+    constexpr int R = 2;
     const int lane = threadIdx.x & 63;
     const int64_t waves = blockDim.x >> 6;
     const float *x = reinterpret_cast<const float *>(p.b);
     float *y = reinterpret_cast<float *>(p.out);
-    for (int64_t r = tl.begin + (threadIdx.x >> 6); r < tl.begin + tl.len; r += waves)
-        gemv_row_group<T, ACC, VB, 1, U>(p.a, x, y, p.m, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
+    const int64_t end = tl.begin + tl.len;
+    for (int64_t r = tl.begin + (threadIdx.x >> 6) * R; r < end; r += waves * R)
+        gemv_row_group<T, ACC, VB, R, U>(p.a, x, y, end, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
 }
 
 // Next tile for the work-group: thread 0 draws it from the shared counter
