@@ -9,8 +9,10 @@
 //                     the work-group that finishes a problem's last tile folds
 //                     that problem's partials in tile order and writes its
 //                     result;
-//   gemv tile      -> each wavefront takes pairs of rows of the tile
-//                     (gemv_row_group).
+//   gemv tile      -> rows that fill one step of the work-group (more than
+//                     half of it): the work-group splits each row with x held
+//                     in registers (gemv_xs_rows); other rows: each wavefront
+//                     takes pairs of rows of the tile (gemv_row_group).
 // Tile-to-work-group assignment is dynamic, but every tile's arithmetic and
 // every combine order are fixed by the plan, so results are deterministic.
 // The last work-group to leave resets the tile counter, so the launch can be
@@ -116,6 +118,26 @@ __device__ __forceinline__ void gemv_tile(const BatchProblem &p, const BatchTile
         gemv_row_group<T, ACC, VB, R, U>(p.a, x, y, end, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
 }
 
+// A gemv tile whose rows one step of the work-group covers: the x-stationary
+// row-split loop of the per-call form over the tile's rows (x loaded once per
+// tile, the work-group's threads splitting each row).
+template <class T, int ACC, int VB, int U>
+__device__ __forceinline__ void gemv_tile_xs(const BatchProblem &p, const BatchTile &tl,
+                                             RowPartT<ACC> (*lds)[16][16])
+{
+    GemvArgs g;
+    g.A = p.a;
+    g.x = reinterpret_cast<const float *>(p.b);
+    g.y = reinterpret_cast<float *>(p.out);
+    g.m = p.m;
+    g.n = p.n;
+    g.lda = p.lda;
+    g.nvec = p.nvec;
+    g.alpha = p.alpha;
+    g.beta = p.beta;
+    gemv_xs_rows<T, ACC, VB, 1, U>(g, tl.begin, 1, tl.begin + tl.len, lds);
+}
+
 // Next tile for the work-group: thread 0 draws it from the shared counter
 // (offset by the grid size: work-group b's first tile is b, taken without
 // an atomic, so the launch does not start with every work-group contending
@@ -145,10 +167,12 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
     using BT = typename BlockT<ACC>::type;
     using ST = typename SlotT<ACC>::type;
     constexpr int EB = T::bytes;  // element-wise loads for unaligned problems
+    constexpr bool XS_TILES = U * Elems<T, VB>::value <= 32;
     __shared__ BT lds_block[16];
     __shared__ ST lds_final[16];
     __shared__ int s_tile;
     __shared__ int s_last;
+    __shared__ RowPartT<ACC> lds_rows[2][16][16];
     const int t = threadIdx.x;
     const int64_t B = blockDim.x;
 
@@ -160,7 +184,13 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
         const int vec = __builtin_amdgcn_readfirstlane(p.vec);
 
         if (kind == KIND_GEMV) {
-            if (vec)
+            // uniform: rows that fill more than half of one step keep x in
+            // registers (instances whose x slice, U x E values, fits next to
+            // the reduction path's registers); shorter rows would leave most of
+            // the work-group idle on each row, so wavefronts take row pairs
+            if (XS_TILES && vec && p.nvec * 2 > B * U && p.nvec <= B * U)
+                gemv_tile_xs<T, ACC, VB, U>(p, tl, lds_rows);
+            else if (vec)
                 gemv_tile<T, ACC, VB, U>(p, tl);
             else
                 gemv_tile<T, ACC, EB, U>(p, tl);

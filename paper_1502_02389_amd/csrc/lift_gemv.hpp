@@ -369,25 +369,27 @@ __device__ __forceinline__ void store_row_part(const GemvArgs &a, int64_t i, Row
 // Row-split form with x held in registers, for rows that one step of the
 // work-group covers (nvec <= B * U).  Thread t needs the same x vectors
 // t, t+B, ..., t+(U-1)B for every row, so it loads them once and each row
-// costs only its A loads; x is read once per work-group instead of once per
-// row.  Row groups are visited grid-stride (r0 = (blockIdx.x + j G) R).
-// Every wave folds its row partial with the butterfly and parks it in LDS;
-// after 16 rows one barrier lets 16 threads fold those rows' wave partials
-// in wave order and store y.  Two LDS banks alternate, so one barrier per 16
-// rows is enough (a bank is rewritten only after the next barrier, which
-// every thread reaches after its reads of that bank).  Lanes, waves and
-// wave partials are folded in the same orders as in gemv_split_kernel.
+// costs only its A loads; x is read once per call instead of once per row.
+// The work-group visits row groups [r0, r0 + R) for r0 = first, first + step,
+// ... below `end` (rows from `end` on are read at a clamped index and never
+// written).  Every wave folds its row partial with the butterfly and parks it
+// in LDS; after 16 rows one barrier lets 16 threads fold those rows' wave
+// partials in wave order and store y.  Two LDS banks alternate, so one
+// barrier per 16 rows is enough (a bank is rewritten only after the next
+// barrier, which every thread reaches after its reads of that bank).  Lanes,
+// waves and wave partials are folded in the same orders as in
+// gemv_split_kernel.  All threads of the work-group must call this with the
+// same arguments (it has barriers).
 template <class T, int ACC, int VB, int R, int U>
-__global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_xs_kernel(GemvArgs a)
+__device__ __forceinline__ void gemv_xs_rows(const GemvArgs &a, int64_t first, int64_t step, int64_t end,
+                                             RowPartT<ACC> (*lds)[16][16])
 {
     constexpr int E = Elems<T, VB>::value;
     constexpr int FL = 16 / R;  // row groups per flush
     using V = typename Vec<VB>::type;
     using LT = RowPartT<ACC>;
-    __shared__ LT lds[2][16][16];  // [bank][row slot][wave]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, waves = blockDim.x >> 6;
     const int64_t B = blockDim.x;
-    const int64_t G = gridDim.x;
     const int64_t row_bytes = a.lda * T::bytes;
     const int64_t tail0 = a.nvec * E;
     const bool has_vec = a.nvec > 0;           // uniform
@@ -410,11 +412,11 @@ __global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_xs_kern
     const float xs = has_tail ? a.x[tail0 + t] : 0.f;
 
     int j = 0;
-    for (int64_t r0 = (int64_t)blockIdx.x * R; r0 < a.m; r0 += G * R, ++j) {  // uniform
+    for (int64_t r0 = first; r0 < end; r0 += step, ++j) {  // uniform
         const char *rows[R];
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            rows[r] = reinterpret_cast<const char *>(a.A) + min(r0 + r, a.m - 1) * row_bytes;
+            rows[r] = reinterpret_cast<const char *>(a.A) + min(r0 + r, end - 1) * row_bytes;
         RowAcc<ACC, E> acc[R];
         if (has_vec) {
             V va[R][U];
@@ -450,11 +452,11 @@ __global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_xs_kern
             if (lane == 0)
                 lds[bank][slot + r][wave] = w;
         }
-        if (j % FL == FL - 1 || r0 + G * R >= a.m) {  // uniform: flush the parked rows
+        if (j % FL == FL - 1 || r0 + step >= end) {  // uniform: flush the parked rows
             __syncthreads();
             if (t < slot + R) {
-                const int64_t row = ((int64_t)blockIdx.x + (int64_t)(j - j % FL + t / R) * G) * R + t % R;
-                if (row < a.m) {
+                const int64_t row = first + (int64_t)(j - j % FL + t / R) * step + t % R;
+                if (row < end) {
                     LT d = lds[bank][t][0];
                     for (int w = 1; w < waves; ++w)
                         d = merge(d, lds[bank][t][w]);
@@ -463,6 +465,14 @@ __global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_xs_kern
             }
         }
     }
+    __syncthreads();  // the caller may reuse the LDS banks
+}
+
+template <class T, int ACC, int VB, int R, int U>
+__global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_xs_kernel(GemvArgs a)
+{
+    __shared__ RowPartT<ACC> lds[2][16][16];  // [bank][row slot][wave]
+    gemv_xs_rows<T, ACC, VB, R, U>(a, (int64_t)blockIdx.x * R, (int64_t)gridDim.x * R, a.m, lds);
 }
 
 template <class T, int ACC, int VB, int R, int U>
