@@ -184,7 +184,7 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
 // one long-lived work-group per CU (fewer partials, shorter combine tail),
 // scal many one-step work-groups, gemv a work-group per row with x held in
 // registers where one step covers a row (row_split 0 = chosen per shape).
-constexpr Knobs DEF_SCAL = {256, 16, 2, 1, 0, 32, 1, 1};
+constexpr Knobs DEF_SCAL = {256, 4, 8, 1, 0, 32, 1, 1};
 constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1, 1, 1};
 constexpr Knobs DEF_GEMV = {256, 16, 8, 1, 0, 0, 0, 1};
 constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1, 1};

@@ -62,7 +62,7 @@ class Fun(Node):
     name: str
 
     def __str__(self):
-        return {"add": "plus"}.get(self.name, self.name)
+        return {"add": "plus", "scale": "mult(a)"}.get(self.name, self.name)
 
 
 @dataclass(frozen=True)
@@ -101,12 +101,13 @@ class Comp(Node):
         return " o ".join(str(p) for p in self.parts)
 
 
-LEVELS = ("", "workgroup", "local", "seq", "global")
+LEVELS = ("", "workgroup", "wave", "local", "seq", "global")  # "wave": a 64-lane wavefront (CDNA)
 
 
 @dataclass(frozen=True)
 class Map(Node):
-    """map(f); after lowering (Fig. 4a) map-workgroup, map-local or map-seq."""
+    """map(f); after lowering (Fig. 4a) map-workgroup, map-local or map-seq,
+    and map-wave for the level between the two that a CDNA wavefront forms."""
 
     f: Node
     level: str = ""
@@ -725,4 +726,184 @@ def derived_knob_points(op: str, n: int, elem_bytes: int = 4, unrolls=(1, 2, 4, 
                 if key not in seen:
                     seen.add(key)
                     out.append((kk, d))
+    return out
+
+
+# ---------------------------------------------------------------- scal and gemv
+
+
+@dataclass(frozen=True)
+class ZipX(Node):
+    """zip(row, x): pairs a row of A with the vector x (gemv's dot(x))."""
+
+    def __str__(self):
+        return "zip(x)"
+
+
+SCALE = Fun("scale")   # mult(a): the element function of scal
+
+
+def high_level_map(op: str) -> Node:
+    """scal = map(mult(a)); gemv (its matrix-vector part) =
+    map(reduce(+, 0) o map(mult) o zip(x)) over the rows of A -- Fig. 5; the
+    scaling by alpha and the zip with beta * y are fused into the store."""
+    if op == "scal":
+        return Map(SCALE)
+    if op == "gemv":
+        return Map(comp(Reduce(ADD, 0), Map(MULT), ZipX()))
+    raise ValueError(f"no high-level expression for {op!r}")
+
+
+@dataclass(frozen=True)
+class ScalChoice:
+    chunk: int   # elements per work-group
+    width: int   # vector width E
+
+
+def derive_scal(c: ScalChoice) -> Derivation:
+    """scal along Fig. 2b: vectorise (4e), split into work-group chunks (3c),
+    map-workgroup over chunks and map-local over the vectors of a chunk (4a)."""
+    d = Derivation(high_level_map("scal"))
+    if c.width > 1:
+        d = d.apply_first(vectorize, _is(Map, level=""), n=c.width)
+    d = d.apply_first(split_join, lambda n: isinstance(n, Map) and not n.level, n=c.chunk // c.width)
+    d = d.apply_first(lower_map, _is(Map, level=""), level="workgroup")
+    return d.apply_first(lower_map, _is(Map, level=""), level="local")
+
+
+@dataclass(frozen=True)
+class GemvChoice:
+    """A lowering of gemv's map over rows: one work-group per R rows, its B
+    lanes splitting each row ("workgroup"), or one wavefront per R rows with
+    W wavefronts per work-group ("wave"); rows read as vectors of E elements,
+    per_lane vectors per lane."""
+
+    form: str
+    rows: int
+    lanes: int      # B for the work-group form, the wavefront width for the wave form
+    waves: int      # W (wave form; 1 otherwise)
+    width: int
+    per_lane: int
+
+
+def _row_dot(d: Derivation, lanes: int, per_lane: int, width: int) -> Derivation:
+    """One row's dot(x) reduced by `lanes` lanes behind reorder and a tree --
+    the work-group body of the reduction derivation applied to a whole row."""
+    elem = lambda n: _element_map(n)                                        # noqa: E731
+    if width > 1:
+        d = d.apply_first(vectorize, elem, n=width)
+        d = _on_comp(d, vector_partial, lambda p: isinstance(p[0], Reduce) and isinstance(p[1], AsScalar), 3)
+    else:
+        d = d.apply_first(reduction, _is(Reduce, seq=False))
+    k = _log2(lanes)
+    d = d.apply_first(part_red_iterate, _is(PartRed), k=k + 1)
+    d = d.apply_first(iterate_peel, _is(Iterate, k=k + 1))
+    d = d.apply_first(part_red_reorder, _is(PartRed), nth=1)
+    d = _on_comp(d, reorder_commute, lambda p: isinstance(p[0], Reorder) and isinstance(p[1], Map), 2)
+    d = d.apply_first(part_red_split, _is(PartRed), nth=1, n=per_lane)
+    d = _split_join_fuse(d, per_lane, lane=True)
+    d = d.apply_first(part_red_to_reduce, _is(PartRed), nth=1)
+    d = d.apply_first(part_red_split, _is(PartRed), n=2)
+    return d.apply_first(part_red_to_reduce, _is(PartRed))
+
+
+def derive_gemv(c: GemvChoice) -> Derivation:
+    """gemv: split the row map into groups of R rows (3c) -- and, in the wave
+    form, those into groups of W (3c) -- derive each row's dot with its lanes,
+    then lower: row groups to map-workgroup (wave form: map-workgroup over W
+    wavefronts, map-wave), the R rows of a group to map-seq, lanes and tree to
+    map-local, elements to map-seq (4a-4c), fusing each lane's reduce-seq (3f)."""
+    if c.form not in ("workgroup", "wave"):
+        raise RuleError("gemv forms: workgroup, wave")
+    d = Derivation(high_level_map("gemv"))
+    row_map = lambda n: isinstance(n, Map) and not n.level and not _element_map(n)  # noqa: E731
+    d = d.apply_first(split_join, row_map, n=c.rows)
+    if c.form == "wave":
+        d = d.apply_first(split_join, row_map, n=c.waves)
+    d = _row_dot(d, c.lanes, c.per_lane, c.width)
+    levels = ["workgroup"] + (["wave"] if c.form == "wave" else []) + ["seq"]
+    for lvl in levels:
+        d = d.apply_first(lower_map, row_map, level=lvl)
+    while any(row_map(n) for _, n in walk(d.expr)):
+        d = d.apply_first(lower_map, row_map, level="local")
+    while any(_element_map(n) for _, n in walk(d.expr)):
+        d = d.apply_first(lower_map, _element_map, level="seq")
+    while any(isinstance(n, Reduce) and not n.seq for _, n in walk(d.expr)):
+        d = d.apply_first(lower_reduce, _is(Reduce, seq=False))
+    d = d.apply_first(lower_reorder, _is(Reorder, stride=0), stride=c.lanes)
+    while True:
+        try:
+            d = _on_comp(d, fuse_reduce_seq, lambda p: isinstance(p[0], Reduce) and p[0].seq
+                         and isinstance(p[1], Map) and p[1].level == "seq", 2)
+        except RuleError:
+            return d
+
+
+def gemv_choices(n: int, elem_bytes: int = 4, wave_lanes: int = 64, lanes=(64, 128, 256, 512, 1024),
+                 rows_wg=(1, 2), rows_wave=(1, 2, 4), waves=(1, 2, 4, 8, 16), widths=None) -> Iterator[GemvChoice]:
+    """Branches for rows of n elements: both forms, rows per group, lanes or
+    wavefronts, vector widths E with E lanes x per-lane runs covering the row."""
+    if widths is None:
+        widths = tuple(w for w in (1, 2, 4, 8) if w * elem_bytes <= 16)
+    for w in widths:
+        for b in lanes:
+            if n % (b * w) == 0:
+                for r in rows_wg:
+                    yield GemvChoice("workgroup", r, b, 1, w, n // (b * w))
+        if n % (wave_lanes * w) == 0:
+            for r, nw in itertools.product(rows_wave, waves):
+                yield GemvChoice("wave", r, wave_lanes, nw, w, n // (wave_lanes * w))
+
+
+def _params(d: Derivation, name: str, key: str) -> list:
+    return [p[key] for nm, p, _ in d.steps if nm == name]
+
+
+def scal_knob_points(n: int, blocks=(64, 128, 256, 512, 1024), unrolls=(1, 2, 4, 8), min_chunk: int = 1 << 11,
+                     max_chunk: int = 1 << 20) -> list:
+    """(knobs, derivation) for scal: every derived chunk and width, with each
+    work-group size B and loads in flight U that make whole steps of the chunk
+    (map-local leaves the work-group size to the launch)."""
+    out = []
+    c = min_chunk
+    while c <= min(max_chunk, n):
+        for w in (1, 2, 4):
+            d = derive_scal(ScalChoice(c, w))
+            vecs = c // w
+            for b, u in itertools.product(blocks, unrolls):
+                if vecs % (b * u) == 0:
+                    out.append(({"block": b, "vec_bytes": 4 * w, "unroll": u, "split": c}, d))
+        c *= 2
+    return out
+
+
+def gemv_kernel_knobs(d: Derivation, elem_bytes: int = 4) -> Optional[dict]:
+    """Launch knobs of the gemv kernel that executes this derivation's
+    lowering (without loads in flight, a launch parameter), or None."""
+    levels = [p["level"] for nm, p, _ in d.steps if nm == "lower_map"]
+    rows = _params(d, "split_join", "n")[0]
+    width = (_params(d, "vectorize", "n") or [1])[0]
+    lanes = _params(d, "lower_reorder", "stride")[0]
+    vb = width * elem_bytes
+    if "wave" in levels:
+        if lanes != 64 or rows not in (1, 2, 4) or vb > 16:
+            return None
+        waves = _params(d, "split_join", "n")[1]
+        return {"row_split": 1, "rows_per_wave": rows, "block": 64 * waves, "vec_bytes": vb}
+    if rows not in (1, 2) or (vb != 16 and vb != elem_bytes) or not 64 <= lanes <= 1024:
+        return None
+    return {"row_split": 2, "rows_per_wave": rows, "block": lanes, "vec_bytes": vb}
+
+
+def gemv_knob_points(n: int, elem_bytes: int = 4, **space) -> list:
+    """(knobs, derivation) for gemv rows of n elements, crossed with the
+    loads in flight each kernel form supports."""
+    out = []
+    for c in gemv_choices(n, elem_bytes, **space):
+        d = derive_gemv(c)
+        k = gemv_kernel_knobs(d, elem_bytes)
+        if k is None:
+            continue
+        for u in ((2, 4, 8) if k["row_split"] == 2 else (1, 2, 4, 8)):
+            out.append((dict(k, unroll=u), d))
     return out

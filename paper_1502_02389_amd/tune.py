@@ -272,12 +272,20 @@ class Operands:
         return best
 
 
-def derived(op: str, storage: str, elements: int):
-    """Knob points of the derivations of asum / dot (rewrite.py): each is the
-    launch of the kernel that executes one derived low-level expression."""
+def derived(op: str, storage: str, elements: int = None, n: int = None):
+    """Knob points of the derivations (rewrite.py) of asum / dot / scal, or of
+    gemv rows of n elements: each is the launch of the kernel that executes
+    one derived low-level expression."""
     from . import rewrite
 
-    return rewrite.derived_knob_points(op, elements, elem_bytes=STORAGE_BYTES[storage])
+    eb = STORAGE_BYTES[storage]
+    if op in ("asum", "dot"):
+        return rewrite.derived_knob_points(op, elements, elem_bytes=eb)
+    if op == "scal":
+        return rewrite.scal_knob_points(elements)
+    if op == "gemv":
+        return rewrite.gemv_knob_points(n, elem_bytes=eb)
+    raise ValueError(f"no derived search for {op}")
 
 
 def tune_one(op, storage, acc, elements=None, m=None, n=None, quick=False, log=None, space="grid"):
@@ -287,9 +295,7 @@ def tune_one(op, storage, acc, elements=None, m=None, n=None, quick=False, log=N
     ops = BatchOperands(storage) if op == "batch" else Operands(op, storage, elements, m, n)
     accc = acc if op == "batch" else B.ACC[acc]
     if space == "derived":
-        if op not in ("asum", "dot"):
-            raise ValueError("derived search covers asum and dot")
-        points = derived(op, storage, elements)
+        points = derived(op, storage, elements, n)
     else:
         points = [(kn, None) for kn in grid(op, storage, quick)]
     results = []
@@ -320,7 +326,7 @@ def main(argv=None):
     ap.add_argument("--top", type=int, default=5)
     ap.add_argument("--verbose", action="store_true", help="print every knob point")
     ap.add_argument("--space", default="grid", choices=("grid", "derived"),
-                    help="grid: fixed knob grid; derived: the kernels of the rewrite derivations (asum, dot)")
+                    help="grid: fixed knob grid; derived: the kernels of the rewrite derivations (asum, dot, scal, gemv)")
     args = ap.parse_args(argv)
 
     import torch
@@ -342,7 +348,7 @@ def main(argv=None):
                 for shp in shapes:
                     if op == "gemv":
                         best, res = tune_one(op, storage, acc, m=shp[0], n=shp[1], quick=args.quick,
-                                             log=log if args.verbose else None)
+                                             log=log if args.verbose else None, space=args.space)
                         elements = shp[0] * shp[1]
                     else:
                         best, res = tune_one(op, storage, acc, elements=shp[0], quick=args.quick,

@@ -34,3 +34,31 @@ def test_derived_knob_points_integer_exact(gpu_device, storage):
             k = L.knobs(**kn)
             got = L.asum(xd, knobs=k).item() if op == "asum" else L.dot(xd, yd, knobs=k).item()
             assert got == (ra if op == "asum" else rd), (kn, str(d.expr))
+
+
+def test_derived_scal_and_gemv_points(gpu_device):
+    from tests.gpu_util import o_gemv
+    import numpy as np
+
+    g = W.gen(82)
+    n = 1 << 20
+    x = W.uniform(n, g)
+    xd = x.to(DEV)
+    want = (x.double() * 2.5).float()
+    for kn, d in R.scal_knob_points(n)[::13]:
+        banner("derived scal", kn)
+        assert torch.equal(L.scal(2.5, xd, knobs=L.knobs(**kn)).cpu(), want), (kn, str(d.expr))
+    for storage, eb in (("f32", 4), ("bf16", 2)):
+        m, cols = 300, 2048
+        A = W.integers((m, cols), -8, 8, g, storage)
+        xv = W.integers(cols, -8, 8, g)
+        y = W.integers(m, -8, 8, g)
+        r, _ = o_gemv(1.0, A, xv, 0.5, y)
+        Ad, xvd = A.to(DEV), xv.to(DEV)
+        pts = R.gemv_knob_points(cols, elem_bytes=eb)
+        assert len(pts) > 50
+        for kn, d in pts[::7]:
+            banner("derived gemv", storage, kn)
+            yd = y.to(DEV)
+            L.gemv(1.0, Ad, xvd, 0.5, yd, knobs=L.knobs(**kn))
+            assert np.array_equal(yd.cpu().numpy().astype(np.float64), r), (kn, str(d.expr))

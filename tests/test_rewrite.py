@@ -17,10 +17,16 @@ from oracle import patterns as P
 from paper_1502_02389_amd import rewrite as R
 
 
+ENV = {}   # alpha of scal, x of gemv (bound by the tests below)
+
+
 def to_fn(e):
     """An executable closure for an expression, built from oracle patterns."""
     if isinstance(e, R.Fun):
-        return {"add": P.add, "abs": P.abs_, "mult": lambda pr: P.mult(pr[0], pr[1]), "id": P.identity}[e.name]
+        return {"add": P.add, "abs": P.abs_, "mult": lambda pr: P.mult(pr[0], pr[1]), "id": P.identity,
+                "scale": lambda v: P.mult(ENV["alpha"], v)}[e.name]
+    if isinstance(e, R.ZipX):
+        return lambda row: P.zip_(row, ENV["x"])
     if isinstance(e, R.Fused):
         acc, elem = to_fn(e.acc), to_fn(e.elem)
         return lambda a, x: acc(a, elem(x))
@@ -151,3 +157,64 @@ def test_unimplementable_forms_get_no_kernel():
         k = R.kernel_knobs(d)
         ok = c.reorder and c.tree and 64 <= c.lanes <= 1024
         assert (k is not None) == ok
+
+
+def test_scal_derivations_are_exact_and_match_the_launch_rules():
+    rng = random.Random(6)
+    x = [rng.randint(-9, 9) for _ in range(1 << 12)]
+    ENV["alpha"] = 3
+    want = [3 * v for v in x]
+    for c in (64, 256, 1024, 4096):
+        for w in (1, 2, 4):
+            d = R.derive_scal(R.ScalChoice(c, w))
+            for _, _, e in d.steps:
+                assert to_fn(e)(x) == want, str(e)
+    n = 1 << 24
+    pts = R.scal_knob_points(n)
+    assert len(pts) > 100
+    for k, d in pts:
+        e = k["vec_bytes"] // 4
+        shape = lowered.launch_shape(n, 4, k["vec_bytes"], k["block"], k["unroll"], k["split"])
+        assert shape.chunk == k["split"] // e and shape.grid == n // k["split"]
+
+
+def test_fig2b_shape_is_derived():
+    d = R.derive_scal(R.ScalChoice(1024, 4))
+    assert str(d.expr) == "asScalar o join o map-workgroup(map-local(vect-4(mult(a)))) o split-256 o asVector-4"
+
+
+def test_gemv_derivations_are_exact():
+    rng = random.Random(7)
+    m, n = 8, 64
+    A = [[rng.randint(-8, 8) for _ in range(n)] for _ in range(m)]
+    ENV["x"] = [rng.randint(-8, 8) for _ in range(n)]
+    want = [sum(a * b for a, b in zip(row, ENV["x"])) for row in A]
+    cs = list(R.gemv_choices(n, 4, wave_lanes=4, lanes=(2, 4, 8), rows_wg=(1, 2), rows_wave=(1, 2, 4),
+                              waves=(1, 2), widths=(1, 2, 4)))
+    assert {c.form for c in cs} == {"workgroup", "wave"} and len(cs) > 20
+    def rows_of(out):   # each row's dot is a one-element array (reduce: T[] -> T[1])
+        return [r[0] for r in out]
+
+    for c in cs:
+        d = R.derive_gemv(c)
+        assert rows_of(to_fn(d.start)(A)) == want
+        for name, params, e in d.steps:
+            assert rows_of(to_fn(e)(A)) == want, (c, name, str(e))
+
+
+def test_gemv_knobs_follow_the_lowering():
+    pts = R.gemv_knob_points(8192)
+    forms = {}
+    for k, d in pts:
+        levels = [p["level"] for nm, p, _ in d.steps if nm == "lower_map"]
+        if k["row_split"] == 1:
+            assert "wave" in levels and k["block"] % 64 == 0 and k["rows_per_wave"] in (1, 2, 4)
+        else:
+            assert "wave" not in levels and k["rows_per_wave"] in (1, 2) and k["vec_bytes"] in (4, 16)
+            assert k["unroll"] in (2, 4, 8)
+        forms[k["row_split"]] = forms.get(k["row_split"], 0) + 1
+    assert forms[1] > 50 and forms[2] > 20
+    # 16-bit storage: element or 16-byte loads for the work-group form
+    for k, _ in R.gemv_knob_points(16384, 2):
+        if k["row_split"] == 2:
+            assert k["vec_bytes"] in (2, 16)
