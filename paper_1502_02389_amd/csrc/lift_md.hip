@@ -13,12 +13,13 @@
 // contiguous bytes per group and step), keeps U index loads in flight, then
 // gathers the U * V neighbour positions (16 bytes each; the position array
 // is small and stays in cache) before any arithmetic.  Empty slots (indices
-// outside [0, n)) gather the particle itself and are masked out.
+// outside [0, n)) load nothing and contribute zero.
 //
 // Per neighbour, in binary32: d = p - q, r2 = (dx dx + dy dy) + dz dz
 // (no contraction: the cutoff test r2 < t^2 is an exact, reproducible
-// decision), then 1/r2 by the hardware reciprocal, s6 = (sigma^2 / r2)^3 and
-// F = 24 eps / r2 * s6 * (2 s6 - 1) * d.
+// decision), then 1/r2 by the hardware reciprocal, s6 = (sigma^2 / r2)^3,
+// f = 24 eps / r2 * s6 * (2 s6 - 1) (zero outside the cutoff) and F += f d
+// by fma.
 #include "lift_device.hpp"
 #include "lift_apps.hpp"
 #include "lift_internal.hpp"
@@ -90,7 +91,9 @@ __global__ void __launch_bounds__(1024) md_kernel(MdArgs a)
             for (int e = 0; e < V; ++e) {
                 const int32_t id = lane_of<V>(iv[u], e);
                 use[u][e] = in_row && (uint32_t)id < n;
-                q[u][e] = pos[use[u][e] ? (int64_t)id : i];
+                q[u][e] = p;  // empty slots load nothing
+                if (use[u][e])
+                    q[u][e] = pos[id];
             }
         }
         loads_in_flight();
@@ -104,10 +107,10 @@ __global__ void __launch_bounds__(1024) md_kernel(MdArgs a)
                 const float s2 = a.sigma2 * r2inv;
                 const float s6 = s2 * s2 * s2;
                 const float fs = a.eps24 * r2inv * s6 * (2.f * s6 - 1.f);
-                const bool hit = use[u][e] && r2 < a.t2;
-                fx += hit ? fs * dx : 0.f;
-                fy += hit ? fs * dy : 0.f;
-                fz += hit ? fs * dz : 0.f;
+                const float fh = use[u][e] && r2 < a.t2 ? fs : 0.f;
+                fx = fmaf(fh, dx, fx);
+                fy = fmaf(fh, dy, fy);
+                fz = fmaf(fh, dz, fz);
             }
     }
     fx = group_sum<L>(fx);
