@@ -244,9 +244,51 @@ def main():
     if not args.no_forms:
         del sets, ptr
         torch.cuda.empty_cache()
-        result["forms"] = forms(L, W, dev, stream, tuple(args.forms.split(",")))
+        precision = {}
+        result["forms"] = forms(L, W, dev, stream, tuple(args.forms.split(",")), precision)
+        if not args.no_cpu_baseline and precision:
+            result["cpu_baseline"]["precision_forms_vs_oracle"] = precision_errors(precision)
 
     print(json.dumps(result), flush=True)
+
+
+def precision_errors(precision):
+    """Part of the CPU-baseline leg: the binary64 oracle on the stored 16-bit
+    inputs of the precision forms, and each GPU result's error against it
+    (asum relative; dot over sum |x y|; gemv worst row over
+    |alpha| sum |A x| + |beta y|)."""
+    import numpy as np
+
+    import oracle
+
+    def bits(t):
+        return t.view(torch_int16()).numpy().view(np.uint16) if str(t.dtype) == "torch.bfloat16" else t.numpy()
+
+    out = {}
+    for storage, (x, y, got) in precision.get("half", {}).items():
+        tag = "bf16" if storage == "bf16" else None
+        xs, ys = bits(x), bits(y)
+        ra = oracle.asum(xs, dtype=tag)
+        rd = oracle.dot(xs, ys, dtype=tag)
+        mass = oracle.dot_absmass(xs, ys, dtype=tag)
+        for (op, acc), v in got.items():
+            err = abs(v - ra) / ra if op == "asum" else abs(v - rd) / mass
+            out[f"{op}_{storage}_{acc}_2^26"] = float(f"{err:.3e}")
+    if "gemv16" in precision:
+        A, x, y, alpha, beta, got = precision["gemv16"]
+        a16 = bits(A)
+        r = oracle.gemv(alpha, a16, x.numpy(), beta, y.numpy(), adtype="bf16")
+        mass = oracle.gemv_absmass(alpha, a16, x.numpy(), beta, y.numpy(), adtype="bf16")
+        for acc, g in got.items():
+            out[f"gemv_bf16_{acc}_16384"] = float(f"{float(np.max(np.abs(g - r) / mass)):.3e}")
+    log("precision forms vs oracle", out)
+    return out
+
+
+def torch_int16():
+    import torch
+
+    return torch.int16
 
 
 def _cpu_model():
@@ -340,7 +382,7 @@ def _time_calls(fn, nsets, stream, reps=50, warm=5):
     return e0.elapsed_time(e1) * 1e3 / reps
 
 
-def forms(L, W, dev, stream, which=FORMS):
+def forms(L, W, dev, stream, which=FORMS, precision=None):
     import torch
 
     lib = L.library()
@@ -389,7 +431,12 @@ def forms(L, W, dev, stream, which=FORMS):
                     assert lib.lift_dot_ex(n, code, xs[i].data_ptr(), ys[i].data_ptr(), acc, L.LIFT_F64,
                                            res.data_ptr(), wsp, wsb, None, sh) == 0
                 rec(f"asum_{storage}_{acc_name}_2^26", _time_calls(ca, ns, stream), 2 * n, 4 * n)
+                if precision is not None:
+                    got = precision.setdefault("half", {}).setdefault(storage, (x, y, {}))[2]
+                    got[("asum", acc_name)] = res.item()
                 rec(f"dot_{storage}_{acc_name}_2^26", _time_calls(cd, ns, stream), 4 * n, 8 * n)
+                if precision is not None:
+                    got[("dot", acc_name)] = res.item()
             del xs, ys
             torch.cuda.empty_cache()
 
@@ -445,11 +492,17 @@ def forms(L, W, dev, stream, which=FORMS):
         Ad, xd, yd = A.to(dev), x.to(dev), y.to(dev)
         nb = 2 * size * size + 4 * size + 8 * size
         fb = 4 * size * size + 4 * size + 8 * size
+        got = {}
         for acc_name, acc in (("f32", 0), ("comp", 1), ("f64combine", 2)):
-            def cg(i, acc=acc):
+            def cg(i, acc=acc, yv=yd):
                 assert lib.lift_gemv_ex(size, size, alpha, L.LIFT_BF16, Ad.data_ptr(), size, xd.data_ptr(), beta,
-                                        yd.data_ptr(), acc, None, sh) == 0
+                                        yv.data_ptr(), acc, None, sh) == 0
             rec(f"gemv_bf16_{acc_name}_{size}", _time_calls(cg, 1, stream, reps=20), nb, fb)
+            y1 = y.to(dev)                  # one call on the original y, for the error report
+            cg(0, yv=y1)
+            got[acc_name] = y1.cpu().numpy().astype("float64")
+        if precision is not None:
+            precision["gemv16"] = (A, x, y, alpha, beta, got)
     return out
 
 
