@@ -126,7 +126,10 @@ typedef struct lift_knobs {
                               registers; else 1) */
     int32_t lanes_per_item; /* MD only: lanes that share one particle's
                               neighbour list: 1, 2, 4, 8 or 16 */
-    int32_t reserved;      /* must be 0 */
+    int32_t interleave;    /* asum / dot only: 0 = each work-group reduces one
+                              contiguous chunk (split); 1 = work-group b takes
+                              steps of block * unroll vectors b, b + G, ...
+                              (grid-stride, G work-groups as split gives) */
 } lift_knobs;
 
 /* ---- plain FP32 forms (Fig. 5) --------------------------------------- */

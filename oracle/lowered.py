@@ -49,6 +49,8 @@ class Shape:
     block: int       # work-group size B
     chunk: int       # vectors per work-group C (a multiple of B * unroll)
     grid: int        # work-groups G
+    step: int = 0    # B * unroll vectors: with interleave, work-group b takes
+    interleave: bool = False   # steps b, b + G, ... instead of one chunk
 
     @property
     def tail(self) -> int:
@@ -56,10 +58,12 @@ class Shape:
 
 
 def launch_shape(n: int, elem_bytes: int, vec_bytes: int, block: int, unroll: int, split: int,
-                 misalign_elems: int = 0, max_workgroups: int = 8192) -> Shape:
+                 misalign_elems: int = 0, max_workgroups: int = 8192, interleave: bool = False) -> Shape:
     """The documented launch rules for an explicit split (elements per chunk).
 
     ``misalign_elems``: how many elements past a vec_bytes boundary x starts.
+    ``interleave``: the work-groups (as many as the split gives) take steps
+    of block * unroll vectors round-robin instead of one chunk each.
     """
     e = vec_bytes // elem_bytes
     head = 0 if misalign_elems % e == 0 else e - misalign_elems % e
@@ -71,7 +75,7 @@ def launch_shape(n: int, elem_bytes: int, vec_bytes: int, block: int, unroll: in
     if -(-nvec // chunk) > max_workgroups:
         chunk = -(-(-(-nvec // max_workgroups)) // step) * step
     grid = max(1, -(-nvec // chunk))
-    return Shape(n, head, e, nvec, block, chunk, grid)
+    return Shape(n, head, e, nvec, block, chunk, grid, step, interleave)
 
 
 def _pairwise(values, add):
@@ -111,15 +115,27 @@ def evaluate(x, shape: Shape, add, absval, zero):
     B, C, E, G = s.block, s.chunk, s.e, s.grid
     head, tail0 = x[: s.head], x[s.head + s.nvec * E:]
     vec_part = list(x[s.head: s.head + s.nvec * E])
-    # ragged last chunk: pad with zero vectors (neutral in the sum; reading 1)
     vectors = P.as_vector(E)(vec_part) if vec_part else []
-    vectors += [P.Vec((zero,) * E)] * (G * C - len(vectors))
+    zero_vec = P.Vec((zero,) * E)
+    if s.interleave:
+        # steps of B * unroll vectors, the last one padded with zero vectors;
+        # work-group b's run is steps b, b + G, ... (join o reorder-stride-G
+        # o split-step), each run padded to whole lanes
+        steps = P.split(s.step)(vectors + [zero_vec] * (-len(vectors) % s.step)) if vectors else []
+        runs = [P.join()(steps[b::G]) for b in range(G)]
+        width = max(len(r) for r in runs) if runs else 0
+        width = -(-max(width, B) // B) * B
+        chunks = [r + [zero_vec] * (width - len(r)) for r in runs]
+    else:
+        # ragged last chunk: pad with zero vectors (neutral in the sum; reading 1)
+        vectors += [zero_vec] * (G * C - len(vectors))
+        chunks = P.split(C)(vectors)
     abs_and_plus = lambda acc, a: add(acc, absval(a))
-    lane_fold = P.reduce_seq(P.vect(E, abs_and_plus), P.Vec((zero,) * E))
+    lane_fold = P.reduce_seq(P.vect(E, abs_and_plus), zero_vec)
 
     partials = []
-    for b, chunk in enumerate(P.split(C)(vectors)):                 # map-workgroup
-        lanes = P.split(C // B)(P.reorder_stride(B)(chunk))         # lane t: t, t+B, ...
+    for b, chunk in enumerate(chunks):                              # map-workgroup
+        lanes = P.split(len(chunk) // B)(P.reorder_stride(B)(chunk))  # lane t: t, t+B, ...
         lane_acc = [list(lane_fold(v)[0]) for v in lanes]           # map-local(reduce-seq)
         if b == 0:
             for t, h in enumerate(head):                            # scalar head

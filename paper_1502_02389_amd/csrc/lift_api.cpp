@@ -132,6 +132,7 @@ struct Knobs {
     int wg_per_cu;
     int row_split;  // 1: wavefront per row group, 2: work-group per row
     int lanes;      // MD: lanes per particle
+    int interleave; // reductions: grid-stride steps instead of contiguous chunks
 };
 
 // Checks the caller's knobs (0 = default) and merges them with defaults.
@@ -175,8 +176,9 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
             return LIFT_EINVAL;
         out->lanes = k->lanes_per_item;
     }
-    if (k->reserved)
+    if (k->interleave < 0 || k->interleave > 1)
         return LIFT_EINVAL;
+    out->interleave = k->interleave;
     return LIFT_OK;
 }
 
@@ -184,12 +186,12 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
 // one long-lived work-group per CU (fewer partials, shorter combine tail),
 // scal many one-step work-groups, gemv a work-group per row with x held in
 // registers where one step covers a row (row_split 0 = chosen per shape).
-constexpr Knobs DEF_SCAL = {256, 4, 8, 1, 0, 32, 1, 1};
-constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1, 1, 1};
-constexpr Knobs DEF_GEMV = {256, 16, 8, 1, 0, 0, 0, 1};
-constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1, 1};
-constexpr Knobs DEF_BS = {256, 4, 4, 1, 0, 16, 1, 1};
-constexpr Knobs DEF_MD = {256, 16, 2, 1, 0, 0, 1, 16};
+constexpr Knobs DEF_SCAL = {256, 4, 8, 1, 0, 32, 1, 1, 0};
+constexpr Knobs DEF_REDUCE = {256, 16, 8, 1, 0, 1, 1, 1, 0};
+constexpr Knobs DEF_GEMV = {256, 16, 8, 1, 0, 0, 0, 1, 0};
+constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1, 1, 0};
+constexpr Knobs DEF_BS = {256, 4, 4, 1, 0, 16, 1, 1, 0};
+constexpr Knobs DEF_MD = {256, 16, 2, 1, 0, 0, 1, 16, 0};
 
 // Split a range of n elements of `ebytes` bytes at base address p into a
 // scalar head (up to the first vb-aligned address), whole vb-byte vectors,
@@ -296,6 +298,10 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
     Knobs def = DEF_REDUCE;
     if (eb == 2 && op == OP_DOT)
         def.unroll = 4;  // two 16-bit streams: 4 loads of each in flight measured best
+    if (eb == 4 && op == OP_DOT) {
+        def.unroll = 4;  // two binary32 streams: grid-stride steps of 4 loads in flight
+        def.interleave = 1;
+    }
     lift_status st = resolve(knobs, def, eb, &k);
     if (st != LIFT_OK)
         return st;
@@ -329,6 +335,7 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
     a.ws = ws;
     a.result = result;
     a.result_f64 = rt == LIFT_F64;
+    a.interleave = k.interleave;
     return launch(kern, grid, k.block, &a, stream);
 }
 

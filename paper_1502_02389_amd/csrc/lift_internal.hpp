@@ -38,6 +38,7 @@ struct ReduceArgs {
     void *ws;          // header + partial slots (unused when the grid is 1)
     void *result;
     int32_t result_f64;
+    int32_t interleave;  // 1: work-group b takes steps b, b + G, ... (grid-stride)
 };
 
 // map(mult(alpha), x) with the same head / vector / tail split.

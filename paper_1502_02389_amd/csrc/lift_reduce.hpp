@@ -275,14 +275,19 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     const char *xv = reinterpret_cast<const char *>(a.x) + a.head * T::bytes;
     const char *yv = OP == OP_DOT ? reinterpret_cast<const char *>(a.y) + a.head * T::bytes : nullptr;
 
-    const int64_t vbeg = (int64_t)blockIdx.x * a.chunk;
-    const int64_t vend = min(vbeg + a.chunk, a.nvec);
+    // The work-group's steps of B * U vectors: one contiguous chunk
+    // (split^chunk), or every G-th step starting at its own (the chunking of
+    // a reorder-stride-G over steps: all work-groups then stream neighbouring
+    // steps at the same time).
     const int64_t step = B * U;
+    const int64_t vbeg = a.interleave ? (int64_t)blockIdx.x * step : (int64_t)blockIdx.x * a.chunk;
+    const int64_t vend = a.interleave ? a.nvec : min(vbeg + a.chunk, a.nvec);
+    const int64_t stride = a.interleave ? (int64_t)gridDim.x * step : step;
 
     LaneAcc<ACC, E> acc;
     int64_t base = vbeg;
     // full steps: U independent loads per lane (per operand) in flight
-    for (; base + step <= vend; base += step) {
+    for (; base + step <= vend; base += stride) {
         V vx[U], vy[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {

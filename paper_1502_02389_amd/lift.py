@@ -47,12 +47,14 @@ class lift_knobs(ctypes.Structure):
         ("wg_per_cu", ctypes.c_int32),
         ("row_split", ctypes.c_int32),
         ("lanes_per_item", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("interleave", ctypes.c_int32),
     ]
 
 
-def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0, wg_per_cu=0, row_split=0, lanes_per_item=0):
-    return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split, wg_per_cu, row_split, lanes_per_item, 0)
+def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0, wg_per_cu=0, row_split=0, lanes_per_item=0,
+          interleave=0):
+    return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split, wg_per_cu, row_split, lanes_per_item,
+                      interleave)
 
 
 LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV = 0, 1, 2

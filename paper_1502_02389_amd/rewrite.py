@@ -22,8 +22,9 @@ its existence (Section 6.3); this module is this library's own.
   parameter or an alternative -- the work-group chunk, the vector width, the
   per-lane split, whether lanes read through ``reorder``, whether lane
   partials are combined by a tree (``iterate`` of pairwise ``part-red``) or by
-  one sequential ``reduce`` -- it branches, and every branch ends in a fully
-  lowered expression.
+  one sequential ``reduce``, whether the work-groups' input is reordered so
+  that they take steps dealt round-robin -- it branches, and every branch
+  ends in a fully lowered expression.
 * ``kernel_knobs`` recognises the expressions this library's streaming
   reduction kernel implements (work-group chunk C, B lanes reading through
   reorder-stride-B, vectors of E elements, a tree over the lanes) and returns
@@ -447,6 +448,14 @@ def lower_reorder(e: Node, stride: int) -> Node:
     return Reorder(stride)
 
 
+def lower_reorder_blocks(e: Node, stride: int, block: int) -> Node:
+    """4c on blocks: reorder -> join o reorder-stride-s o split-b, the
+    permutation that deals blocks of b elements round-robin to s groups."""
+    if not isinstance(e, Reorder) or e.stride:
+        raise RuleError("expects an unlowered reorder")
+    return comp(Join(), Reorder(stride), Split(block))
+
+
 def to_local(e: Node) -> Node:
     """4d: f -> toLocal(f) (results kept in local memory)."""
     return ToLocal(e)
@@ -532,6 +541,9 @@ class Choice:
     per_lane: int     # vectors per lane (split inside a work-group)
     reorder: bool     # lanes read through reorder (-stride) or contiguous runs
     tree: bool        # lane partials combined by iterate(part-red) or one reduce
+    interleave: int = 0   # > 0: work-groups take steps of `interleave` vectors
+    #                       round-robin (a reorder of the input by blocks)
+    groups: int = 0       # the number of work-groups the steps are dealt to
 
     @property
     def lanes(self) -> int:
@@ -597,6 +609,9 @@ def derive_one(op: str, c: Choice) -> Derivation:
         d = _on_comp(d, vector_partial, lambda p: isinstance(p[0], Reduce) and isinstance(p[1], AsScalar), 3)
     else:
         d = d.apply_first(reduction, _is(Reduce, seq=False))               # reduce o part-red
+    if c.interleave:                                                       # work-groups on dealt steps
+        d = d.apply_first(part_red_reorder, _is(PartRed))
+        d = _on_comp(d, reorder_commute, lambda p: isinstance(p[0], Reorder) and isinstance(p[1], Map), 2)
     d = d.apply_first(part_red_split, _is(PartRed), n=vecs)                # join o map(part-red) o split
     d = _split_join_fuse(d, vecs, lane=False)                              # map(part-red o map(f)) o split
     if lanes == 1:
@@ -632,8 +647,11 @@ def _lower(d: Derivation, c: Choice) -> Derivation:
         d = d.apply_first(lower_map, _element_map, level="seq")
     while any(isinstance(n, Reduce) and not n.seq for _, n in walk(d.expr)):
         d = d.apply_first(lower_reduce, _is(Reduce, seq=False))
-    if any(isinstance(n, Reorder) for _, n in walk(d.expr)):
-        d = d.apply_first(lower_reorder, _is(Reorder, stride=0), stride=c.lanes)
+    in_wg = [p for p, n in walk(d.expr) if isinstance(n, Reorder) and not n.stride and len(p) > 1]
+    if in_wg:                                        # lanes: reorder-stride-B inside the work-group
+        d = d.apply(lower_reorder, in_wg[0], stride=c.lanes)
+    if c.interleave:                                 # work-groups: steps dealt round-robin
+        d = d.apply_first(lower_reorder_blocks, _is(Reorder, stride=0), stride=c.groups, block=c.interleave)
     while True:
         try:
             d = _on_comp(d, fuse_reduce_seq, lambda p: isinstance(p[0], Reduce) and p[0].seq
@@ -643,9 +661,10 @@ def _lower(d: Derivation, c: Choice) -> Derivation:
 
 
 def choices(n: int, widths=(1, 2, 4), lanes=(1, 64, 128, 256, 512, 1024), min_chunk: int = 1 << 11,
-            max_chunk: int = 1 << 20) -> Iterator[Choice]:
+            max_chunk: int = 1 << 20, interleave: bool = True) -> Iterator[Choice]:
     """The branches explored for an input of n elements (powers of two that
-    divide n): work-group chunk, vector width, lanes, reorder, tree."""
+    divide n): work-group chunk, vector width, lanes, reorder, tree, and
+    whether work-groups take one chunk or steps dealt round-robin."""
     c = min_chunk
     while c <= min(max_chunk, n):
         if n % c == 0:
@@ -654,6 +673,11 @@ def choices(n: int, widths=(1, 2, 4), lanes=(1, 64, 128, 256, 512, 1024), min_ch
                     forms = [(False, False)] if b == 1 else itertools.product((True, False), (True, False))
                     for reorder, tree in forms:
                         yield Choice(c, w, c // (w * b), reorder, tree)
+                    if b > 1 and interleave:
+                        p = c // (w * b)
+                        for u in (1, 2, 4, 8):
+                            if p % u == 0 and n // c > 1:
+                                yield Choice(c, w, p, True, True, interleave=b * u, groups=n // c)
         c *= 2
 
 
@@ -681,7 +705,10 @@ def kernel_knobs(d: Derivation, elem_bytes: int = 4) -> Optional[dict]:
     vb = c.width * elem_bytes
     if vb > 16 or vb < min(4, elem_bytes):
         return None
-    return {"block": c.lanes, "vec_bytes": vb, "split": c.chunk}
+    k = {"block": c.lanes, "vec_bytes": vb, "split": c.chunk}
+    if c.interleave:
+        k.update(interleave=1, unroll=c.interleave // c.lanes)   # the dealt step is block x unroll
+    return k
 
 
 def _choice_of(d: Derivation) -> Optional[Choice]:
@@ -696,7 +723,9 @@ def _choice_of(d: Derivation) -> Optional[Choice]:
     vecs = splits[0]
     per_lane = splits[1] if len(splits) > 1 else vecs
     tree = bool(iters) and len(splits) > 2 and splits[2] == 2
-    c = Choice(vecs * width, width, per_lane, bool(strides), tree)
+    blocks = [(p["stride"], p["block"]) for name, p, _ in d.steps if name == "lower_reorder_blocks"]
+    il, groups = (blocks[0][1], blocks[0][0]) if blocks else (0, 0)
+    c = Choice(vecs * width, width, per_lane, bool(strides), tree, il, groups)
     if strides and strides[0] != c.lanes:
         return None
     if tree and iters[0] != _log2(c.lanes) + 1:
@@ -719,6 +748,12 @@ def derived_knob_points(op: str, n: int, elem_bytes: int = 4, unrolls=(1, 2, 4, 
         if k is None or n // k["split"] > max_workgroups:
             continue
         per_lane = k["split"] // (k["vec_bytes"] // elem_bytes) // k["block"]
+        if "unroll" in k:                      # the derivation fixes the step
+            key = tuple(sorted(k.items()))
+            if key not in seen:
+                seen.add(key)
+                out.append((k, d))
+            continue
         for u in unrolls:
             if per_lane % u == 0:
                 kk = dict(k, unroll=u)

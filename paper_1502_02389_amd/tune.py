@@ -126,6 +126,8 @@ def grid(op: str, storage: str, quick: bool = False):
         (0, 1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
     for b, v, u, s in itertools.product(blocks, vecs, (1, 2, 4, 8), splits):
         yield dict(block=b, vec_bytes=v, unroll=u, split=s)
+        if op in ("asum", "dot"):
+            yield dict(block=b, vec_bytes=v, unroll=u, split=s, interleave=1)
 
 
 # ---------------------------------------------------------------- timing

@@ -62,7 +62,7 @@ def test_enum_values_match_header():
 
 
 def test_struct_layouts():
-    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, row_split, lanes_per_item, reserved
+    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, row_split, lanes_per_item, interleave
     assert ctypes.sizeof(B.lift_knobs) == 40
     assert B.lift_knobs.split.offset == 16 and B.lift_knobs.wg_per_cu.offset == 24
     assert B.lift_knobs.lanes_per_item.offset == 32
@@ -177,9 +177,8 @@ def test_ex_rejects_bad_enums_and_knobs():
     assert L.lift_blackscholes_ex(8, X, 20.0, 0.02, 0.3, 1.0, Y, B.knobs(block=100)) == L.LIFT_EINVAL
     for bad in (B.knobs(lanes_per_item=3), B.knobs(lanes_per_item=32), B.knobs(unroll=8), B.knobs(vec_bytes=2)):
         assert L.lift_md_ex(8, X, 4, Y, 2.5, 1.0, 1.0, R, bad) == L.LIFT_EINVAL
-    bad = B.knobs()
-    bad.reserved = 1
-    assert L.lift_md_ex(8, X, 4, Y, 2.5, 1.0, 1.0, R, bad) == L.LIFT_EINVAL
+    for bad in (B.knobs(interleave=2), B.knobs(interleave=-1)):
+        assert L.lift_asum_ex(8, 0, X, 0, 0, R, WS, w, bad) == L.LIFT_EINVAL
 
 
 @cpu_only

@@ -138,10 +138,11 @@ def test_reduce_every_knob_point_integer_bitexact(gpu_device):
     rd, _ = o_dot(x, y)
     xd, yd = x.to(DEV), y.to(DEV)
     for b, v, u, s in KNOB_POINTS:
-        k = L.knobs(block=b, vec_bytes=v, unroll=u, split=s)
-        banner("knobs", b, v, u, s)
-        assert L.asum(xd, knobs=k).item() == ra, (b, v, u, s)
-        assert L.dot(xd, yd, knobs=k).item() == rd, (b, v, u, s)
+        for il in (0, 1):
+            k = L.knobs(block=b, vec_bytes=v, unroll=u, split=s, interleave=il)
+            banner("knobs", b, v, u, s, il)
+            assert L.asum(xd, knobs=k).item() == ra, (b, v, u, s, il)
+            assert L.dot(xd, yd, knobs=k).item() == rd, (b, v, u, s, il)
 
 
 def test_reduce_every_knob_point_uniform(gpu_device):
@@ -152,9 +153,9 @@ def test_reduce_every_knob_point_uniform(gpu_device):
     ra = o_asum(x)
     rd, mass = o_dot(x, y)
     xd, yd = x.to(DEV), y.to(DEV)
-    for b, v, u, s in KNOB_POINTS[::3]:
-        k = L.knobs(block=b, vec_bytes=v, unroll=u, split=s)
-        banner("knobs uniform", b, v, u, s)
+    for i, (b, v, u, s) in enumerate(KNOB_POINTS[::3]):
+        k = L.knobs(block=b, vec_bytes=v, unroll=u, split=s, interleave=i % 2)
+        banner("knobs uniform", b, v, u, s, i % 2)
         assert rel(L.asum(xd, knobs=k).item(), ra) <= TOL
         assert abs(L.dot(xd, yd, knobs=k).item() - rd) <= TOL * mass
 

@@ -25,7 +25,11 @@ F32 = dict(add=lambda a, b: np.float32(a) + np.float32(b), absval=lambda a: np.f
            zero=np.float32(0))
 
 CASES = [
-    # n, offset (elements), storage, block, vec_bytes, unroll, split
+    # n, offset (elements), storage, block, vec_bytes, unroll, split[, interleave]
+    (70_001, 0, "f32", 256, 16, 8, 1 << 15, 1),
+    (1 << 20, 0, "f32", 256, 16, 4, 1 << 16, 1),
+    (300_007, 2, "f32", 128, 4, 2, 1 << 12, 1),
+    (100_000, 1, "bf16", 256, 16, 4, 1 << 15, 1),
     (70_001, 0, "f32", 256, 16, 8, 1 << 15),
     (70_001, 1, "f32", 64, 16, 1, 256),
     (200_003, 3, "f32", 1024, 8, 4, 1 << 17),
@@ -38,18 +42,21 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"{c[2]}-n{c[0]}-o{c[1]}-b{c[3]}-v{c[4]}-u{c[5]}-s{c[6]}" for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[2]}-n{c[0]}-o{c[1]}-b{c[3]}-v{c[4]}-u{c[5]}-s{c[6]}"
+                                             f"{'-il' if len(c) > 7 else ''}" for c in CASES])
 def test_asum_matches_lowered_expression_bitwise(gpu_device, case):
-    n, off, storage, block, vb, unroll, split = case
+    n, off, storage, block, vb, unroll, split = case[:7]
+    il = len(case) > 7 and case[7] == 1
     x = W.uniform(n, W.gen(800 + n % 1000 + off), storage)
     buf = torch.empty(n + off, dtype=x.dtype, device=DEV)
     xd = buf[off:]
     xd.copy_(x.to(DEV))
     assert xd.data_ptr() % vb == (off * EB[storage]) % vb
     banner("lowered asum", case)
-    k = L.knobs(block=block, vec_bytes=vb, unroll=unroll, split=split)
+    k = L.knobs(block=block, vec_bytes=vb, unroll=unroll, split=split, interleave=int(il))
     g = L.asum(xd, knobs=k).item()
-    shape = LW.launch_shape(n, EB[storage], vb, block, unroll, split, misalign_elems=off % (vb // EB[storage]))
+    shape = LW.launch_shape(n, EB[storage], vb, block, unroll, split, misalign_elems=off % (vb // EB[storage]),
+                            interleave=il)
     vals = [np.float32(v) for v in x.float().numpy()]
     pred = LW.evaluate(vals, shape, **F32)
     assert np.float32(g).view(np.uint32) == np.float32(pred).view(np.uint32), (g, float(pred), LW.render(shape))

@@ -4,6 +4,7 @@ generalised to the library's knobs): on integer inputs it equals the plain
 sum exactly, for every knob point, size and misalignment."""
 import random
 
+import numpy as np
 import pytest
 
 from oracle import lowered as LW
@@ -34,9 +35,10 @@ def test_every_tuner_knob_point_is_a_valid_derivation(storage, eb):
     for block, vb, unroll, split in knob_points(storage):
         n = r.choice([0, 1, 5, 1000, 4099, 50_000])
         mis = r.randrange(vb // eb)
-        s = LW.launch_shape(n, eb, vb, block, unroll, split, misalign_elems=mis)
         x = ints(n, block + vb + unroll + n)
-        assert LW.evaluate(x, s, **EXACT) == sum(abs(v) for v in x), (block, vb, unroll, split, n, mis)
+        for il in (False, True):
+            s = LW.launch_shape(n, eb, vb, block, unroll, split, misalign_elems=mis, interleave=il)
+            assert LW.evaluate(x, s, **EXACT) == sum(abs(v) for v in x), (block, vb, unroll, split, n, mis, il)
 
 
 @pytest.mark.parametrize("n", [0, 1, 3, 63, 64, 65, 4095, 70_001])
@@ -87,3 +89,20 @@ def test_binary32_evaluation_distinguishes_trees():
         assert abs(float(a) - float(b)) <= 1e-5 * float(a)
         differ += a != b
     assert differ >= 1
+
+
+def test_interleaved_runs_are_a_permutation_of_the_chunks():
+    # the same vectors reach the lanes, in a different grouping: with every
+    # vector distinct, each work-group run holds steps b, b + G, ... in order
+    s = LW.launch_shape(10_000, 4, 16, 64, 2, 1 << 10, interleave=True)
+    assert s.step == 128 and s.grid == -(-2500 // s.chunk)
+    x = list(range(1, 10_001))
+    add = lambda a, b: a + b                                  # noqa: E731
+    assert LW.evaluate(x, s, add=add, absval=lambda v: v, zero=0) == sum(x)
+    f32 = dict(add=lambda a, b: np.float32(a) + np.float32(b), absval=lambda a: np.float32(abs(a)),
+               zero=np.float32(0))
+    rng = np.random.default_rng(3)
+    vals = [np.float32(v) for v in rng.uniform(-1, 1, 100_000).astype(np.float32)]
+    a = LW.evaluate(vals, LW.launch_shape(100_000, 4, 16, 256, 4, 1 << 14), **f32)
+    b = LW.evaluate(vals, LW.launch_shape(100_000, 4, 16, 256, 4, 1 << 14, interleave=True), **f32)
+    assert a != b          # a different association, visible in binary32

@@ -62,8 +62,8 @@ def run(e, data):
     return out[0]
 
 
-N = 1 << 12
-SPACE = dict(widths=(1, 2, 4), lanes=(1, 4, 8, 16), min_chunk=1 << 6, max_chunk=1 << 10)
+N = 1 << 11
+SPACE = dict(widths=(1, 2, 4), lanes=(1, 4, 8, 16), min_chunk=1 << 6, max_chunk=1 << 9)
 
 
 @pytest.fixture(scope="module")
@@ -124,15 +124,21 @@ def test_knobs_reproduce_the_derived_partition(op):
     n = 1 << 24
     pts = R.derived_knob_points(op, n)
     assert len(pts) > 100
+    dealt = 0
     for k, d in pts:
         c = R._choice_of(d)
         e = k["vec_bytes"] // 4
-        shape = lowered.launch_shape(n, 4, k["vec_bytes"], k["block"], k["unroll"], k["split"])
+        il = bool(k.get("interleave"))
+        shape = lowered.launch_shape(n, 4, k["vec_bytes"], k["block"], k["unroll"], k["split"], interleave=il)
         assert shape.e == c.width == e
         assert shape.block == c.lanes
         assert shape.chunk == c.chunk // e              # vectors per work-group
         assert shape.grid == n // c.chunk
         assert shape.head == 0 and shape.tail == 0
+        if il:                                          # the dealt steps and their groups
+            dealt += 1
+            assert shape.step == c.interleave and shape.grid == c.groups
+    assert dealt > 50
 
 
 def test_rules_check_their_preconditions():
