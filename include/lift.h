@@ -91,6 +91,19 @@ typedef enum lift_acc {
                                    for the cross-lane combine of each row) */
 } lift_acc;
 
+/* Values of lift_knobs.interleave: how the work-groups of asum and dot
+ * divide the vectors among themselves (the work-group level of the paper's
+ * reorder, Section 3.3 and Fig. 9). */
+typedef enum lift_interleave {
+    LIFT_INTERLEAVE_DEFAULT = 0, /* library choice: STRIDE for dot, CHUNK
+                                    for asum */
+    LIFT_INTERLEAVE_STRIDE = 1,  /* work-group b takes steps of block * unroll
+                                    vectors b, b + G, b + 2G, ... (G
+                                    work-groups, as many as split gives) */
+    LIFT_INTERLEAVE_CHUNK = 2    /* work-group b reduces one contiguous chunk
+                                    of split elements */
+} lift_interleave;
+
 /* Launch knobs: the parameters the paper's low-level expressions expose
  * (split factor, work-group size, vector width; Fig. 9 and Section 6.2)
  * plus the rows handled together by one wavefront in gemv.  A zero field
@@ -126,10 +139,7 @@ typedef struct lift_knobs {
                               registers; else 1) */
     int32_t lanes_per_item; /* MD only: lanes that share one particle's
                               neighbour list: 1, 2, 4, 8 or 16 */
-    int32_t interleave;    /* asum / dot only: 0 = each work-group reduces one
-                              contiguous chunk (split); 1 = work-group b takes
-                              steps of block * unroll vectors b, b + G, ...
-                              (grid-stride, G work-groups as split gives) */
+    int32_t interleave;    /* asum / dot only: a lift_interleave value */
 } lift_knobs;
 
 /* ---- plain FP32 forms (Fig. 5) --------------------------------------- */

@@ -132,7 +132,7 @@ struct Knobs {
     int wg_per_cu;
     int row_split;  // 1: wavefront per row group, 2: work-group per row
     int lanes;      // MD: lanes per particle
-    int interleave; // reductions: grid-stride steps instead of contiguous chunks
+    int interleave; // reductions: 1 = grid-stride steps, 0 = contiguous chunks
 };
 
 // Checks the caller's knobs (0 = default) and merges them with defaults.
@@ -176,9 +176,10 @@ lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
             return LIFT_EINVAL;
         out->lanes = k->lanes_per_item;
     }
-    if (k->interleave < 0 || k->interleave > 1)
+    if (k->interleave < LIFT_INTERLEAVE_DEFAULT || k->interleave > LIFT_INTERLEAVE_CHUNK)
         return LIFT_EINVAL;
-    out->interleave = k->interleave;
+    if (k->interleave)
+        out->interleave = k->interleave == LIFT_INTERLEAVE_STRIDE;
     return LIFT_OK;
 }
 
@@ -296,10 +297,8 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
         return LIFT_EINVAL;
     Knobs k;
     Knobs def = DEF_REDUCE;
-    if (eb == 2 && op == OP_DOT)
-        def.unroll = 4;  // two 16-bit streams: 4 loads of each in flight measured best
-    if (eb == 4 && op == OP_DOT) {
-        def.unroll = 4;  // two binary32 streams: grid-stride steps of 4 loads in flight
+    if (op == OP_DOT) {
+        def.unroll = 4;  // two streams: grid-stride steps of 4 loads of each in flight
         def.interleave = 1;
     }
     lift_status st = resolve(knobs, def, eb, &k);

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "liblift.so")
 LIFT_OK, LIFT_EINVAL, LIFT_EWORKSPACE, LIFT_EHIP, LIFT_EUNSUPPORTED = 0, -1, -2, -3, -4
 LIFT_F32, LIFT_BF16, LIFT_F16, LIFT_F64 = 0, 1, 2, 3
 LIFT_ACC_F32, LIFT_ACC_F32_COMP, LIFT_ACC_F32_F64COMBINE = 0, 1, 2
+LIFT_INTERLEAVE_DEFAULT, LIFT_INTERLEAVE_STRIDE, LIFT_INTERLEAVE_CHUNK = 0, 1, 2
 
 ACC = {"f32": LIFT_ACC_F32, "comp": LIFT_ACC_F32_COMP, "f64combine": LIFT_ACC_F32_F64COMBINE}
 

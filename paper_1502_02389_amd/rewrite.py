@@ -43,6 +43,9 @@ import itertools
 from dataclasses import dataclass, field
 from typing import Callable, Iterator, Optional, Tuple
 
+# lift_knobs.interleave values (the work-group partition of asum / dot)
+INTERLEAVE_STRIDE, INTERLEAVE_CHUNK = 1, 2
+
 # ---------------------------------------------------------------- expressions
 
 
@@ -705,9 +708,9 @@ def kernel_knobs(d: Derivation, elem_bytes: int = 4) -> Optional[dict]:
     vb = c.width * elem_bytes
     if vb > 16 or vb < min(4, elem_bytes):
         return None
-    k = {"block": c.lanes, "vec_bytes": vb, "split": c.chunk}
-    if c.interleave:
-        k.update(interleave=1, unroll=c.interleave // c.lanes)   # the dealt step is block x unroll
+    k = {"block": c.lanes, "vec_bytes": vb, "split": c.chunk, "interleave": INTERLEAVE_CHUNK}
+    if c.interleave:                                 # the dealt step is block x unroll
+        k.update(interleave=INTERLEAVE_STRIDE, unroll=c.interleave // c.lanes)
     return k
 
 

@@ -125,9 +125,11 @@ def grid(op: str, storage: str, quick: bool = False):
     splits = (0, 1 << 15, 1 << 16, 1 << 17, 1 << 18) if quick else \
         (0, 1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
     for b, v, u, s in itertools.product(blocks, vecs, (1, 2, 4, 8), splits):
-        yield dict(block=b, vec_bytes=v, unroll=u, split=s)
         if op in ("asum", "dot"):
-            yield dict(block=b, vec_bytes=v, unroll=u, split=s, interleave=1)
+            yield dict(block=b, vec_bytes=v, unroll=u, split=s, interleave=B.LIFT_INTERLEAVE_CHUNK)
+            yield dict(block=b, vec_bytes=v, unroll=u, split=s, interleave=B.LIFT_INTERLEAVE_STRIDE)
+        else:
+            yield dict(block=b, vec_bytes=v, unroll=u, split=s)
 
 
 # ---------------------------------------------------------------- timing

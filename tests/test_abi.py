@@ -177,7 +177,7 @@ def test_ex_rejects_bad_enums_and_knobs():
     assert L.lift_blackscholes_ex(8, X, 20.0, 0.02, 0.3, 1.0, Y, B.knobs(block=100)) == L.LIFT_EINVAL
     for bad in (B.knobs(lanes_per_item=3), B.knobs(lanes_per_item=32), B.knobs(unroll=8), B.knobs(vec_bytes=2)):
         assert L.lift_md_ex(8, X, 4, Y, 2.5, 1.0, 1.0, R, bad) == L.LIFT_EINVAL
-    for bad in (B.knobs(interleave=2), B.knobs(interleave=-1)):
+    for bad in (B.knobs(interleave=3), B.knobs(interleave=-1)):
         assert L.lift_asum_ex(8, 0, X, 0, 0, R, WS, w, bad) == L.LIFT_EINVAL
 
 
@@ -258,3 +258,23 @@ def test_batch_null_handles():
 def test_batch_valid_plan_without_gpu_reports_hip_error():
     assert _batch_status([dict(kind=0, n=16, a=X, out=R),
                           dict(kind=2, m=8, n=16, lda=16, a=Y, b=WS, out=R + 256, alpha=1.0, beta=0.5)]) == L.LIFT_EHIP
+
+
+def test_names_used_by_gpu_tests_and_bench_exist():
+    # the GPU tests only run on a GPU; a name they take from the package
+    # that does not exist would surface there first, so check it here
+    import glob
+
+    import paper_1502_02389_amd as pkg
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    files = glob.glob(os.path.join(root, "tests", "*.py")) + [os.path.join(root, "bench.py"),
+                                                                os.path.join(root, "__graft_entry__.py")]
+    missing = []
+    for f in files:
+        src = open(f).read()
+        if "import paper_1502_02389_amd as L" not in src:
+            continue
+        missing += [(os.path.basename(f), n) for n in set(re.findall(r"\bL\.([A-Za-z_]\w*)", src))
+                    if not hasattr(pkg, n)]
+    assert not missing, missing

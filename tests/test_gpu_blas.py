@@ -138,11 +138,43 @@ def test_reduce_every_knob_point_integer_bitexact(gpu_device):
     rd, _ = o_dot(x, y)
     xd, yd = x.to(DEV), y.to(DEV)
     for b, v, u, s in KNOB_POINTS:
-        for il in (0, 1):
+        for il in (L.LIFT_INTERLEAVE_CHUNK, L.LIFT_INTERLEAVE_STRIDE):
             k = L.knobs(block=b, vec_bytes=v, unroll=u, split=s, interleave=il)
             banner("knobs", b, v, u, s, il)
             assert L.asum(xd, knobs=k).item() == ra, (b, v, u, s, il)
             assert L.dot(xd, yd, knobs=k).item() == rd, (b, v, u, s, il)
+
+
+def test_interleave_default_is_stride_for_dot_chunk_for_asum(gpu_device):
+    # interleave 0 leaves the partition to the library: grid-stride steps for
+    # dot, contiguous chunks for asum.  The input is built so the two
+    # partitions give different, exactly known sums.  Knobs: 256 lanes x 4
+    # loads = steps of 1024 vectors, split 2^15 elements -> G = 128
+    # work-groups over n = 2^22.  Step s holds v_s in its first element;
+    # v_1 = v_2 = v_3 = 100, v_G = 2^30, everything else 0.
+    #   chunk:  work-group 0 owns steps 0..S-1 (S >= 4): partial 300 exactly;
+    #           2^30 sits in another work-group; combine: 2^30 + 300 -> 2^30 + 256
+    #   stride: work-group 0 owns steps 0, G, ...: partial 2^30; work-groups
+    #           1, 2, 3 hold 100 each; any balanced combine tree rounds
+    #           2^30 + 100 up to 2^30 + 128, then + 200 to 2^30 + 384
+    # (binary32 spacing at 2^30 is 128).
+    n, G = 1 << 22, 128
+    chunk, stride = L.LIFT_INTERLEAVE_CHUNK, L.LIFT_INTERLEAVE_STRIDE
+    base = dict(block=256, vec_bytes=16, unroll=4, split=1 << 15)
+    want = {chunk: 2.0 ** 30 + 256, stride: 2.0 ** 30 + 384}
+    for storage, eb in (("f32", 4), ("bf16", 2)):
+        e = 16 // eb
+        x = torch.zeros(n)
+        x[[1024 * e, 2048 * e, 3072 * e]] = 100.0
+        x[G * 1024 * e] = 2.0 ** 30
+        xd = x.to(W.STORAGE[storage]).to(DEV)
+        yd = torch.ones(n, dtype=W.STORAGE[storage], device=DEV)
+        banner("interleave default", storage)
+        for il in (chunk, stride):
+            assert L.asum(xd, knobs=L.knobs(**base, interleave=il)).item() == want[il], (storage, il)
+            assert L.dot(xd, yd, knobs=L.knobs(**base, interleave=il)).item() == want[il], (storage, il)
+        assert L.asum(xd, knobs=L.knobs(**base)).item() == want[chunk]
+        assert L.dot(xd, yd, knobs=L.knobs(**base)).item() == want[stride]
 
 
 def test_reduce_every_knob_point_uniform(gpu_device):
@@ -154,7 +186,8 @@ def test_reduce_every_knob_point_uniform(gpu_device):
     rd, mass = o_dot(x, y)
     xd, yd = x.to(DEV), y.to(DEV)
     for i, (b, v, u, s) in enumerate(KNOB_POINTS[::3]):
-        k = L.knobs(block=b, vec_bytes=v, unroll=u, split=s, interleave=i % 2)
+        k = L.knobs(block=b, vec_bytes=v, unroll=u, split=s,
+                    interleave=(L.LIFT_INTERLEAVE_CHUNK, L.LIFT_INTERLEAVE_STRIDE)[i % 2])
         banner("knobs uniform", b, v, u, s, i % 2)
         assert rel(L.asum(xd, knobs=k).item(), ra) <= TOL
         assert abs(L.dot(xd, yd, knobs=k).item() - rd) <= TOL * mass

@@ -53,7 +53,8 @@ def test_asum_matches_lowered_expression_bitwise(gpu_device, case):
     xd.copy_(x.to(DEV))
     assert xd.data_ptr() % vb == (off * EB[storage]) % vb
     banner("lowered asum", case)
-    k = L.knobs(block=block, vec_bytes=vb, unroll=unroll, split=split, interleave=int(il))
+    k = L.knobs(block=block, vec_bytes=vb, unroll=unroll, split=split,
+                interleave=L.LIFT_INTERLEAVE_STRIDE if il else L.LIFT_INTERLEAVE_CHUNK)
     g = L.asum(xd, knobs=k).item()
     shape = LW.launch_shape(n, EB[storage], vb, block, unroll, split, misalign_elems=off % (vb // EB[storage]),
                             interleave=il)

@@ -99,7 +99,7 @@ def test_fig9b_shape_is_derived():
         "iterate-8(join o map-local(reduce-seq(vect-4(plus), vect-4(0))) o split-2) o join o "
         "map-local(reduce-seq(vect-4(absAndPlus), vect-4(0))) o split-2 o reorder-stride-256) o "
         "split-512 o asVector-4")
-    assert R.kernel_knobs(d) == {"block": 256, "vec_bytes": 16, "split": 2048}
+    assert R.kernel_knobs(d) == {"block": 256, "vec_bytes": 16, "split": 2048, "interleave": R.INTERLEAVE_CHUNK}
     # Fig. 9c: one lane per work-group, no reorder -- derived, but not this library's kernel
     d = R.derive_one("asum", R.Choice(32768, 4, 8192, False, False))
     assert str(d.expr) == ("reduce-seq(plus, 0) o asScalar o join o map-workgroup(reduce-seq(vect-4(absAndPlus), "
@@ -128,7 +128,7 @@ def test_knobs_reproduce_the_derived_partition(op):
     for k, d in pts:
         c = R._choice_of(d)
         e = k["vec_bytes"] // 4
-        il = bool(k.get("interleave"))
+        il = k["interleave"] == R.INTERLEAVE_STRIDE
         shape = lowered.launch_shape(n, 4, k["vec_bytes"], k["block"], k["unroll"], k["split"], interleave=il)
         assert shape.e == c.width == e
         assert shape.block == c.lanes
