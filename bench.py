@@ -47,7 +47,7 @@ sys.path.insert(0, ROOT)
 PEAK_GBS = 8000.0
 METRIC = "HBM GB/s and % of 8 TB/s peak: asum/dot/gemv FP32 vs BF16 and batched forms"
 COLD_BYTES = 1 << 30          # rotate buffer sets until at least this much is touched
-FORMS = ("gemv", "half", "batch", "blackscholes", "md", "gemv16")
+FORMS = ("small", "gemv", "half", "batch", "blackscholes", "md", "gemv16")
 
 
 def log(*a):
@@ -382,6 +382,35 @@ def _time_calls(fn, nsets, stream, reps=50, warm=5):
     return e0.elapsed_time(e1) * 1e3 / reps
 
 
+def _time_graph(fn, nsets, stream, reps=50, warm=5):
+    """Average device time per call of fn(i, stream_handle) over reps calls
+    captured in one HIP graph and replayed: for launch-bound kernels, whose
+    back-to-back host launches would leave the device idle between them."""
+    import torch
+
+    for i in range(warm):
+        fn(i % nsets, stream.cuda_stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for i in range(reps):
+                fn(i % nsets, side.cuda_stream)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    del g
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
 def forms(L, W, dev, stream, which=FORMS, precision=None):
     import torch
 
@@ -412,6 +441,22 @@ def forms(L, W, dev, stream, which=FORMS, precision=None):
             rec(f"gemv_f32_{size}", _time_calls(call, ns, stream), nb, nb)
             del As
             torch.cuda.empty_cache()
+
+    if "small" in which:
+        # asum fp32 n = 2^20 (4 MiB): uniform and integer inputs.  The kernel
+        # runs ~5 us, less than a host launch through Python takes, so the
+        # launches are captured in a HIP graph and timed as one replay.
+        for kind in ("uniform", "integer"):
+            x = W.asum_small_vector(integer=kind == "integer")
+            n = x.numel()
+            ns = max(2, -(-COLD_BYTES // (4 * n)))
+            xs = [x.to(dev) for _ in range(ns)]
+            res = torch.zeros((), dtype=torch.float32, device=dev)
+
+            def ca(i, h, xs=xs, res=res, n=n):
+                assert lib.lift_asum(n, xs[i].data_ptr(), res.data_ptr(), wsp, wsb, h) == 0
+            rec(f"asum_f32_{kind}_2^20", _time_graph(ca, ns, stream), 4 * n, 4 * n)
+            del xs
 
     if "half" in which:
         # 16-bit storage asum / dot, n = 2^26
