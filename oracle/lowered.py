@@ -1,4 +1,4 @@
-"""Low-level asum expressions for a launch configuration (TEST INFRASTRUCTURE).
+"""Low-level asum / dot expressions for a launch configuration (TEST INFRASTRUCTURE).
 
 The paper lowers ``asum = reduce(+,0) . map(abs)`` to device-specific
 expressions built from its OpenCL patterns (Fig. 9, Section 6.2), choosing
@@ -27,8 +27,15 @@ first and last work-group.
 ``evaluate(x, shape, add)`` runs the expression with a caller-given binary
 ``add``: with exact integer arithmetic it must equal asum (every knob point
 is a valid derivation), and with IEEE binary32 addition it predicts the
-library's floating-point result bit for bit.  Shares no code with the GPU
-library.
+library's floating-point result bit for bit.
+
+``evaluate_dot(x, y, shape, add, fma)`` does the same for
+``dot = reduce(+,0) . map(*) . zip`` (Fig. 5): the work-group and lane
+structure is the asum one, over ``zip(asVector-E x, asVector-E y)``, and the
+lane step is ``reduce-seq(vect-E(multAndPlus))`` with multAndPlus(acc, a, b)
+= fma(a, b, acc) (the fused form of rule 3f; reading 7 allows the
+contraction); head and tail pairs enter component 0 of their lanes the same
+way.  Shares no code with the GPU library.
 """
 from __future__ import annotations
 
@@ -112,26 +119,60 @@ def evaluate(x, shape: Shape, add, absval, zero):
     s = shape
     if len(x) != s.n:
         raise ValueError("input length differs from the launch shape")
-    B, C, E, G = s.block, s.chunk, s.e, s.grid
-    head, tail0 = x[: s.head], x[s.head + s.nvec * E:]
+    E = s.e
     vec_part = list(x[s.head: s.head + s.nvec * E])
     vectors = P.as_vector(E)(vec_part) if vec_part else []
+    abs_and_plus = lambda acc, a: add(acc, absval(a))
+    lane_step = P.vect(E, abs_and_plus)                      # vect-E(absAndPlus)
+    scalar_step = abs_and_plus
+    return _launch(vectors, P.Vec((zero,) * E), x[: s.head], x[s.head + s.nvec * E:], s, lane_step,
+                   scalar_step, add, zero)
+
+
+def evaluate_dot(x, y, shape: Shape, add, fma, zero):
+    """The low-level expression of one dot launch on the lists x and y.
+
+    fma(a, b, c) is a * b + c with the arithmetic's rounding (one rounding in
+    binary32; exact on integers), add(a, b) the tree's addition.
+    """
+    s = shape
+    if len(x) != s.n or len(y) != s.n:
+        raise ValueError("input length differs from the launch shape")
+    E = s.e
+    lo, hi = s.head, s.head + s.nvec * E
+    xv = P.as_vector(E)(list(x[lo:hi])) if hi > lo else []
+    yv = P.as_vector(E)(list(y[lo:hi])) if hi > lo else []
+    pairs = P.zip_(xv, yv)                                    # zip(asVector x, asVector y)
+    mult_and_plus = lambda acc, a, b: fma(a, b, acc)
+    lane_vect = P.vect(E, mult_and_plus)                      # vect-E(multAndPlus)
+    lane_step = lambda acc, pair: lane_vect(acc, pair[0], pair[1])
+    scalar_step = lambda acc, pair: mult_and_plus(acc, pair[0], pair[1])
+    zero_vec = P.Vec((zero,) * E)
+    head = list(zip(x[:lo], y[:lo]))
+    tail = list(zip(x[hi:], y[hi:]))
+    return _launch(pairs, (zero_vec, zero_vec), head, tail, s, lane_step, scalar_step, add, zero)
+
+
+def _launch(vectors, zero_item, head, tail0, s: Shape, lane_step, scalar_step, add, zero):
+    """The launch's partition and trees over the vector items (vectors, or
+    pairs of vectors for dot); head / tail items enter lane component 0 of
+    the first / last work-group through scalar_step."""
+    B, C, E, G = s.block, s.chunk, s.e, s.grid
     zero_vec = P.Vec((zero,) * E)
     if s.interleave:
         # steps of B * unroll vectors, the last one padded with zero vectors;
         # work-group b's run is steps b, b + G, ... (join o reorder-stride-G
         # o split-step), each run padded to whole lanes
-        steps = P.split(s.step)(vectors + [zero_vec] * (-len(vectors) % s.step)) if vectors else []
+        steps = P.split(s.step)(vectors + [zero_item] * (-len(vectors) % s.step)) if vectors else []
         runs = [P.join()(steps[b::G]) for b in range(G)]
         width = max(len(r) for r in runs) if runs else 0
         width = -(-max(width, B) // B) * B
-        chunks = [r + [zero_vec] * (width - len(r)) for r in runs]
+        chunks = [r + [zero_item] * (width - len(r)) for r in runs]
     else:
-        # ragged last chunk: pad with zero vectors (neutral in the sum; reading 1)
-        vectors += [zero_vec] * (G * C - len(vectors))
+        # ragged last chunk: pad with zero items (neutral in the sum; reading 1)
+        vectors = list(vectors) + [zero_item] * (G * C - len(vectors))
         chunks = P.split(C)(vectors)
-    abs_and_plus = lambda acc, a: add(acc, absval(a))
-    lane_fold = P.reduce_seq(P.vect(E, abs_and_plus), zero_vec)
+    lane_fold = P.reduce_seq(lane_step, zero_vec)
 
     partials = []
     for b, chunk in enumerate(chunks):                              # map-workgroup
@@ -139,10 +180,10 @@ def evaluate(x, shape: Shape, add, absval, zero):
         lane_acc = [list(lane_fold(v)[0]) for v in lanes]           # map-local(reduce-seq)
         if b == 0:
             for t, h in enumerate(head):                            # scalar head
-                lane_acc[t][0] = add(lane_acc[t][0], absval(h))
+                lane_acc[t][0] = scalar_step(lane_acc[t][0], h)
         if b == G - 1:
             for t, v in enumerate(tail0):                           # scalar tail
-                lane_acc[t][0] = add(lane_acc[t][0], absval(v))
+                lane_acc[t][0] = scalar_step(lane_acc[t][0], v)
         lane_vals = [_pairwise(acc, add) for acc in lane_acc]      # iterate-log2(E)
         partials.append(_block_tree(lane_vals, add))                # toLocal tree
     if G == 1:

@@ -16,7 +16,7 @@ import torch
 import paper_1502_02389_amd as L
 import workloads as W
 from oracle import lowered as LW
-from tests.gpu_util import banner, o_asum, rel
+from tests.gpu_util import banner, o_asum, o_dot, rel
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -62,3 +62,100 @@ def test_asum_matches_lowered_expression_bitwise(gpu_device, case):
     pred = LW.evaluate(vals, shape, **F32)
     assert np.float32(g).view(np.uint32) == np.float32(pred).view(np.uint32), (g, float(pred), LW.render(shape))
     assert rel(g, o_asum(x)) <= 1e-5
+
+
+# dot: n, x offset, y offset (elements), storage, block, vec_bytes, unroll, split, interleave
+DOT_CASES = [
+    (70_001, 0, 0, "f32", 256, 16, 4, 1 << 15, True),
+    (70_001, 0, 0, "f32", 256, 16, 4, 1 << 15, False),
+    (1 << 20, 0, 0, "f32", 256, 16, 4, 1 << 16, True),
+    (300_007, 2, 2, "f32", 128, 8, 2, 1 << 12, True),
+    (200_003, 3, 3, "f32", 1024, 16, 1, 1 << 17, False),
+    (100_000, 1, 1, "bf16", 256, 16, 4, 1 << 15, True),
+    (100_000, 5, 5, "f16", 512, 8, 2, 1 << 14, False),
+    (50_003, 0, 1, "f32", 256, 16, 4, 1 << 13, True),       # phases differ: element loads
+    (7, 0, 0, "f32", 256, 16, 8, 1 << 15, True),
+]
+
+
+@pytest.mark.parametrize("case", DOT_CASES, ids=[f"{c[3]}-n{c[0]}-o{c[1]}.{c[2]}-b{c[4]}-v{c[5]}-u{c[6]}-s{c[7]}"
+                                                 f"{'-il' if c[8] else ''}" for c in DOT_CASES])
+def test_dot_matches_lowered_expression_bitwise(gpu_device, case):
+    from tests import binary32 as F32B
+
+    n, ox, oy, storage, block, vb, unroll, split, il = case
+    g = W.gen(900 + n % 1000 + ox + 7 * oy)
+    x = W.uniform(n, g, storage)
+    y = W.uniform(n, g, storage)
+    bx = torch.empty(n + ox, dtype=x.dtype, device=DEV)
+    by = torch.empty(n + oy, dtype=y.dtype, device=DEV)
+    xd, yd = bx[ox:], by[oy:]
+    xd.copy_(x.to(DEV))
+    yd.copy_(y.to(DEV))
+    banner("lowered dot", case)
+    k = L.knobs(block=block, vec_bytes=vb, unroll=unroll, split=split,
+                interleave=L.LIFT_INTERLEAVE_STRIDE if il else L.LIFT_INTERLEAVE_CHUNK)
+    got = L.dot(xd, yd, knobs=k).item()
+    eb = EB[storage]
+    same_phase = (ox * eb) % vb == (oy * eb) % vb
+    vbytes = vb if same_phase else eb                         # different phases: element loads
+    shape = LW.launch_shape(n, eb, vbytes, block, unroll, split, misalign_elems=(ox * eb % vb) // eb if same_phase
+                            else 0, interleave=il)
+    xs = [float(v) for v in x.float().numpy()]
+    ys = [float(v) for v in y.float().numpy()]
+    pred = LW.evaluate_dot(xs, ys, shape, add=F32B.add, fma=F32B.fma, zero=0.0)
+    assert np.float32(got).view(np.uint32) == np.float32(pred).view(np.uint32), (got, pred, LW.render(shape))
+    r, mass = o_dot(x, y)
+    assert abs(got - r) <= 1e-5 * mass
+
+
+_STEP = {}
+
+
+def _step_run():
+    """The bench step's asum and dot (n = 2^24, seed 1) through the plain
+    entry points with the library's default launch; results and inputs."""
+    if not _STEP:
+        x, y, _ = W.stream_vectors()
+        n = x.numel()
+        xd, yd = x.to(DEV), y.to(DEV)
+        ws = L.workspace(DEV)
+        res = torch.zeros(2, dtype=torch.float32, device=DEV)
+        s = torch.cuda.current_stream().cuda_stream
+        banner("step kernels 2^24 default launch")
+        assert L.lift_asum(n, xd.data_ptr(), res[0:].data_ptr(), ws.data_ptr(), ws.numel(), s) == 0
+        assert L.lift_dot(n, xd.data_ptr(), yd.data_ptr(), res[1:].data_ptr(), ws.data_ptr(), ws.numel(), s) == 0
+        _STEP.update(res=res.cpu().numpy(), xs=[float(v) for v in x.numpy()], ys=[float(v) for v in y.numpy()],
+                     cus=torch.cuda.get_device_properties(0).multi_processor_count)
+    return _STEP
+
+
+def _default_split(n, cus):
+    # default launch: 256 lanes, 16-byte vectors, one chunk per compute unit
+    return -(-(n // 4) // cus) * 4
+
+
+def test_step_asum_2p24_default_launch_matches_its_expression(gpu_device):
+    """asum of the bench step, default launch (contiguous chunks, 8 loads in
+    flight, ~1 work-group per compute unit): bit for bit."""
+    from tests import binary32 as F32B
+
+    st = _step_run()
+    n = len(st["xs"])
+    sa = LW.launch_shape(n, 4, 16, 256, 8, _default_split(n, st["cus"]))
+    assert sa.grid == st["cus"]
+    pa = LW.evaluate(st["xs"], sa, add=F32B.add, absval=abs, zero=0.0)
+    assert np.float32(st["res"][0]).view(np.uint32) == np.float32(pa).view(np.uint32), (float(st["res"][0]), pa)
+
+
+def test_step_dot_2p24_default_launch_matches_its_expression(gpu_device):
+    """dot of the bench step (the roofline kernel), default launch
+    (grid-stride steps of 4 loads per operand): bit for bit."""
+    from tests import binary32 as F32B
+
+    st = _step_run()
+    n = len(st["xs"])
+    sd = LW.launch_shape(n, 4, 16, 256, 4, _default_split(n, st["cus"]), interleave=True)
+    assert sd.grid == st["cus"]
+    pd = LW.evaluate_dot(st["xs"], st["ys"], sd, add=F32B.add, fma=F32B.fma, zero=0.0)
+    assert np.float32(st["res"][1]).view(np.uint32) == np.float32(pd).view(np.uint32), (float(st["res"][1]), pd)

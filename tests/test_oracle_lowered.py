@@ -106,3 +106,54 @@ def test_interleaved_runs_are_a_permutation_of_the_chunks():
     a = LW.evaluate(vals, LW.launch_shape(100_000, 4, 16, 256, 4, 1 << 14), **f32)
     b = LW.evaluate(vals, LW.launch_shape(100_000, 4, 16, 256, 4, 1 << 14, interleave=True), **f32)
     assert a != b          # a different association, visible in binary32
+
+
+@pytest.mark.parametrize("storage,eb", [("f32", 4), ("bf16", 2)])
+def test_every_tuner_knob_point_is_a_valid_dot_derivation(storage, eb):
+    # the dot expression (zip of the vectorised operands, lane fold with
+    # multAndPlus, the asum trees) equals the dot product exactly on integers
+    r = random.Random(2)
+    exact = dict(add=lambda a, b: a + b, fma=lambda a, b, c: a * b + c, zero=0)
+    for block, vb, unroll, split in list(knob_points(storage))[::3]:
+        n = r.choice([0, 1, 5, 1000, 4099, 50_000])
+        mis = r.randrange(vb // eb)
+        x, y = ints(n, block + n), ints(n, vb + unroll + n)
+        want = sum(a * b for a, b in zip(x, y))
+        for il in (False, True):
+            s = LW.launch_shape(n, eb, vb, block, unroll, split, misalign_elems=mis, interleave=il)
+            assert LW.evaluate_dot(x, y, s, **exact) == want, (block, vb, unroll, split, n, mis, il)
+
+
+def test_dot_expression_is_the_asum_expression_on_abs_values():
+    # with y = 1 and x >= 0, multAndPlus(acc, a, 1) = acc + a = absAndPlus:
+    # the two expressions must coincide bit for bit in binary32 (same
+    # partition, same trees), for both work-group partitions
+    from tests import binary32 as F
+
+    rng = np.random.default_rng(4)
+    vals = [float(v) for v in rng.uniform(0, 1, 30_011).astype(np.float32)]
+    ones = [1.0] * len(vals)
+    for il in (False, True):
+        s = LW.launch_shape(len(vals), 4, 16, 128, 2, 1 << 12, misalign_elems=1, interleave=il)
+        d = LW.evaluate_dot(vals, ones, s, add=F.add, fma=F.fma, zero=0.0)
+        a = LW.evaluate(vals, s, add=F.add, absval=abs, zero=0.0)
+        assert d == a
+
+
+def test_dot_expression_fma_is_one_rounding():
+    # the lane step is a fused multiply-add.  a = 1 + 2^-23: a * a = 1 + 2^-22
+    # + 2^-46 rounds to 1 + 2^-22.  Lane t folds x[t] * y[t] then x[t+64] *
+    # y[t+64] (reorder-stride-64, one work-group, one element per vector);
+    # with x = (a, ..., -a, ...), y = a: fma leaves the product's low part,
+    # -2^-46 per lane, a rounded multiply then add leaves 0
+    from tests import binary32 as F
+
+    a = float(np.float32(1 + 2.0 ** -23))
+    x = [a] * 64 + [-a] * 64
+    y = [a] * 128
+    s = LW.launch_shape(128, 4, 4, 64, 1, 128)
+    assert s.grid == 1 and s.chunk == 128
+    fused = LW.evaluate_dot(x, y, s, add=F.add, fma=F.fma, zero=0.0)
+    unfused = LW.evaluate_dot(x, y, s, add=F.add, fma=lambda p, q, c: F.add(F.to_binary32(p * q), c), zero=0.0)
+    assert fused == -64 * 2.0 ** -46
+    assert unfused == 0.0
