@@ -215,3 +215,23 @@ def render(shape: Shape) -> str:
     text = (f"reduce-seq o join o map-workgroup(\n      {wg}\n    ) o split-{s.chunk} o asVector-{s.e}"
             f"   [{s.grid} work-groups x {waves} waves; head {s.head}, tail {s.tail} scalars]")
     return text
+
+
+def evaluate_gemv_rows(rows, x, alpha, beta, y, shape: Shape, add, mul, fma, zero):
+    """gemv's low-level expression for the given rows (Fig. 5,
+    ``map(scal(alpha) o dot(x))`` over rows zipped with ``scal(beta, y)``):
+    each row's dot is the dot expression of ``shape`` with one work-group
+    (or one wavefront, block 64) per row -- lane t folds vectors t, t + B,
+    ... of the row, the column tail enters lanes' component 0 -- then
+    y_i' = fma(alpha, dot_i, beta * y_i), with beta * y_i taken as zero when
+    beta is zero (BLAS: y is not read; reading 10) and alpha applied once to
+    the finished dot (reading 8).  ``rows`` and ``y`` are parallel lists;
+    ``shape`` must describe a single work-group (grid 1)."""
+    if shape.grid != 1:
+        raise ValueError("a row is reduced by one work-group")
+    out = []
+    for row, yi in zip(rows, y):
+        d = evaluate_dot(list(row)[: shape.n], x, shape, add=add, fma=fma, zero=zero)
+        by = zero if beta == 0 else mul(beta, yi)
+        out.append(fma(alpha, d, by))
+    return out

@@ -44,3 +44,7 @@ def fma(a, b, c) -> float:
     if e != 0.0 and _last_bit(s) == 0:
         s = math.nextafter(s, math.inf if e > 0 else -math.inf)
     return to_binary32(s)
+
+
+def mul(a, b) -> float:
+    return to_binary32(float(a) * float(b))

@@ -159,3 +159,70 @@ def test_step_dot_2p24_default_launch_matches_its_expression(gpu_device):
     assert sd.grid == st["cus"]
     pd = LW.evaluate_dot(st["xs"], st["ys"], sd, add=F32B.add, fma=F32B.fma, zero=0.0)
     assert np.float32(st["res"][1]).view(np.uint32) == np.float32(pd).view(np.uint32), (float(st["res"][1]), pd)
+
+
+# gemv: m, n, lda, storage, knobs (row_split, block, rows_per_wave, unroll, vec_bytes) -> the
+# row expression's lanes (64 for a wavefront per row, the work-group size otherwise)
+GEMV_CASES = [
+    (97, 1001, 1008, "f32", dict(row_split=1, rows_per_wave=1, unroll=4, vec_bytes=16), 64),
+    (97, 1001, 1008, "f32", dict(row_split=1, rows_per_wave=2, unroll=2, vec_bytes=16), 64),
+    (61, 5000, 5000, "f32", dict(row_split=2, block=256, rows_per_wave=1, unroll=4, vec_bytes=16), 256),
+    (61, 3000, 3004, "f32", dict(row_split=2, block=256, rows_per_wave=2, unroll=4, vec_bytes=16), 256),
+    (50, 1001, 1001, "f32", dict(row_split=2, block=128, rows_per_wave=1, unroll=8, vec_bytes=16), 128),
+    (64, 9000, 9000, "bf16", dict(row_split=2, block=256, rows_per_wave=1, unroll=8, vec_bytes=16), 256),
+    (33, 777, 784, "f16", dict(row_split=1, rows_per_wave=4, unroll=2, vec_bytes=8), 64),
+]
+
+
+def _gemv_model_rows(A, x, y, alpha, beta, rows, lanes, unroll, vec_bytes, eb):
+    from tests import binary32 as F32B
+
+    n = x.numel()
+    shape = LW.launch_shape(n, eb, vec_bytes, lanes, unroll, max(n, 1))     # one chunk: the whole row
+    xs = [float(v) for v in x.numpy()]
+    Af = A.float().numpy()
+    return LW.evaluate_gemv_rows([[float(v) for v in Af[i, :n]] for i in rows], xs, float(alpha), float(beta),
+                                 [float(y[i]) for i in rows], shape, add=F32B.add, mul=F32B.mul, fma=F32B.fma,
+                                 zero=0.0)
+
+
+@pytest.mark.parametrize("case", GEMV_CASES, ids=[f"{c[3]}-{c[0]}x{c[1]}-lda{c[2]}-rs{c[4]['row_split']}-"
+                                                  f"r{c[4]['rows_per_wave']}-u{c[4]['unroll']}" for c in GEMV_CASES])
+def test_gemv_matches_lowered_rows_bitwise(gpu_device, case):
+    m, n, lda, storage, kn, lanes = case
+    g = W.gen(950 + m + n)
+    A = W.normal((m, lda), g, storage)
+    x = W.normal(n, g)
+    y = W.normal(m, g)
+    alpha, beta = 0.75, -1.25
+    banner("lowered gemv", case)
+    yd = y.to(DEV)
+    L.gemv(alpha, A.to(DEV), x.to(DEV), beta, yd, lda=lda, knobs=L.knobs(**kn))
+    eb = EB[storage]
+    aligned = (lda * eb) % kn["vec_bytes"] == 0
+    pred = _gemv_model_rows(A, x, y, alpha, beta, range(m), lanes, kn["unroll"],
+                            kn["vec_bytes"] if aligned else eb, eb)
+    got = yd.cpu().numpy()
+    bad = [i for i in range(m) if np.float32(got[i]).view(np.uint32) != np.float32(pred[i]).view(np.uint32)]
+    assert not bad, (bad[:5], [(float(got[i]), pred[i]) for i in bad[:3]])
+
+
+@pytest.mark.parametrize("size,sample", [(4096, 128), (8192, 48)])
+def test_gemv_default_launch_sampled_rows_bitwise(gpu_device, size, sample):
+    """gemv fp32 at the bench's sizes through the plain entry point (library
+    default launch: a work-group per row sized to it, x in registers, 8 loads
+    in flight), sampled rows against the row expression bit for bit."""
+    A, x, y, alpha, beta = W.gemv_square(size)
+    banner("lowered gemv default", size)
+    yd = y.to(DEV)
+    Ad, xd = A.to(DEV), x.to(DEV)
+    assert L.lift_gemv(size, size, alpha, Ad.data_ptr(), size, xd.data_ptr(), beta, yd.data_ptr(),
+                       torch.cuda.current_stream().cuda_stream) == 0
+    got = yd.cpu().numpy()
+    block = 64                                    # the documented choice: smallest work-group whose
+    while block * 8 < size // 4 and block < 512:  # one step of 8 loads covers the row
+        block *= 2
+    rows = sorted(np.random.default_rng(size).choice(size, sample, replace=False).tolist())
+    pred = _gemv_model_rows(A, x, y, alpha, beta, rows, block, 8, 16, 4)
+    bad = [i for i, p in zip(rows, pred) if np.float32(got[i]).view(np.uint32) != np.float32(p).view(np.uint32)]
+    assert not bad, bad[:5]

@@ -157,3 +157,27 @@ def test_dot_expression_fma_is_one_rounding():
     unfused = LW.evaluate_dot(x, y, s, add=F.add, fma=lambda p, q, c: F.add(F.to_binary32(p * q), c), zero=0.0)
     assert fused == -64 * 2.0 ** -46
     assert unfused == 0.0
+
+
+@pytest.mark.parametrize("n,vb,block,unroll", [(1000, 16, 64, 4), (1001, 4, 256, 2), (4099, 16, 512, 8), (3, 16, 64, 1),
+                                               (0, 16, 64, 1)])
+def test_gemv_rows_expression_exact_on_integers(n, vb, block, unroll):
+    m = 7
+    A = [ints(n, 10 * i + n) for i in range(m)]
+    x = ints(n, 99)
+    y = ints(m, 98)
+    s = LW.launch_shape(n, 4, vb, block, unroll, max(n, 1))
+    exact = dict(add=lambda a, b: a + b, mul=lambda a, b: a * b, fma=lambda a, b, c: a * b + c, zero=0)
+    for alpha, beta in ((3, 2), (-1, 0), (0, 5)):
+        got = LW.evaluate_gemv_rows(A, x, alpha, beta, y, s, **exact)
+        want = [alpha * sum(a * b for a, b in zip(row, x)) + beta * yi for row, yi in zip(A, y)]
+        assert got == want
+
+
+def test_gemv_rows_beta_zero_does_not_read_y():
+    from tests import binary32 as F
+
+    s = LW.launch_shape(8, 4, 16, 64, 1, 32)
+    got = LW.evaluate_gemv_rows([[1.0] * 8], [2.0] * 8, 0.5, 0.0, [float("nan")], s, add=F.add, mul=F.mul, fma=F.fma,
+                                zero=0.0)
+    assert got == [8.0]
