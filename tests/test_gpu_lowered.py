@@ -226,3 +226,64 @@ def test_gemv_default_launch_sampled_rows_bitwise(gpu_device, size, sample):
     pred = _gemv_model_rows(A, x, y, alpha, beta, rows, block, 8, 16, 4)
     bad = [i for i, p in zip(rows, pred) if np.float32(got[i]).view(np.uint32) != np.float32(p).view(np.uint32)]
     assert not bad, bad[:5]
+
+
+BATCH_KNOBS = [dict(block=256, vec_bytes=16, unroll=4, split=65536, wg_per_cu=2),
+               dict(block=64, vec_bytes=4, unroll=1, split=256, wg_per_cu=1),
+               dict(block=512, vec_bytes=16, unroll=8, split=1 << 15, wg_per_cu=4),
+               dict(block=256, vec_bytes=8, unroll=2, split=4096, wg_per_cu=8)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("kn", BATCH_KNOBS, ids=[str(i) for i in range(len(BATCH_KNOBS))])
+def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
+    """The batched form runs each reduction as the per-call expression with
+    the batch's tiles for work-group chunks (split rounded up to whole steps,
+    partials folded by the last tile's work-group like the per-call combine)
+    and each gemv row as the row expression (a work-group per row where the
+    row fills more than half of one step and fits in it and U x E <= 32,
+    else a wavefront per row; element loads where x or the rows are not
+    aligned).  Every result bit for bit."""
+    from tests import binary32 as F32B
+    from tests.test_gpu_batch import build, small_spec
+
+    cpu, problems = build(small_spec(seed=48, n_red=100, n_gemv=10), storage=storage, seed=49)
+    banner("lowered batch", storage, kn)
+    b = L.Batch(problems, knobs=L.knobs(**kn))
+    b.run()
+    torch.cuda.synchronize()
+    eb = EB[storage]
+    B, U, vb, split = kn["block"], kn["unroll"], kn["vec_bytes"], kn["split"]
+    E = vb // eb
+    for i, (item, pr) in enumerate(zip(cpu, problems)):
+        if item[0] == "gemv":
+            alpha, A, x, beta, y, n = item[1]
+            xd, yd = pr[3], pr[5]
+            lda = A.shape[1]
+            vec = n > 0 and (lda * eb) % vb == 0 and xd.data_ptr() % min(E * 4, 16) == 0
+            nvec = n // E if vec else n
+            xs_rows = U * E <= 32 and vec and 2 * nvec > B * U and nvec <= B * U
+            lanes = B if xs_rows else 64
+            pred = _gemv_model_rows(A, x[:n].contiguous(), y, alpha, beta, range(A.shape[0]), lanes, U,
+                                    vb if vec else eb, eb)
+            got = yd.cpu().numpy()
+            bad = [r for r in range(A.shape[0])
+                   if np.float32(got[r]).view(np.uint32) != np.float32(pred[r]).view(np.uint32)]
+            assert not bad, (i, "gemv", bad[:4])
+        else:
+            kind, x, y = item
+            xd = pr[1]
+            n = x.numel()
+            mis = (xd.data_ptr() % vb) // eb
+            same = kind == "asum" or pr[2].data_ptr() % vb == xd.data_ptr() % vb
+            shape = LW.launch_shape(n, eb, vb if same else eb, B, U, split, misalign_elems=mis if same else 0,
+                                    max_workgroups=1 << 30)
+            xs = [float(v) for v in x.float().numpy()]
+            if kind == "asum":
+                pred = LW.evaluate(xs, shape, add=F32B.add, absval=abs, zero=0.0)
+            else:
+                ys = [float(v) for v in y.float().numpy()]
+                pred = LW.evaluate_dot(xs, ys, shape, add=F32B.add, fma=F32B.fma, zero=0.0)
+            got = b.results[i].item()
+            assert np.float32(got).view(np.uint32) == np.float32(pred).view(np.uint32), (i, kind, n, got, pred)
+    b.close()
