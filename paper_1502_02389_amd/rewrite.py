@@ -1,4 +1,4 @@
-"""Rewrite-driven derivation of reduction kernels (the paper's Section 4 rules).
+"""Rewrite-driven derivation of the kernels' low-level expressions (the paper's Section 4 rules).
 
 The paper expresses a program as a composition of algorithmic patterns and
 derives device-specific low-level expressions by applying semantics-preserving
@@ -31,6 +31,12 @@ its existence (Section 6.3); this module is this library's own.
   the launch knobs that execute exactly that partition of the input; other
   expressions (one lane per work-group, lanes on contiguous runs, a
   sequential combine of the lanes) have no kernel here and give ``None``.
+* ``derive_scal`` lowers ``map(mult(a))`` along Fig. 2b (vectorise, split
+  into work-group chunks, map-workgroup / map-local), and ``derive_gemv``
+  splits gemv's map over rows into groups of R rows, lowered to work-groups
+  or, through a ``map-wave`` level for the 64-lane wavefront, to wavefronts,
+  each row's dot being the reduction derivation; ``scal_knob_points`` and
+  ``gemv_knob_points`` map them to launches the same way.
 
 The autotuner times the kernels of the derived expressions
 (``tune.py --space derived``); the tests evaluate every step of every
