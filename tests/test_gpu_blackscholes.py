@@ -3,8 +3,9 @@
 Bar: every call and put within 1e-5 of the binary64 oracle, measured against
 the magnitude of the two terms of the formula, s + K e^{-rT} (deep
 out-of-the-money prices are tiny differences of those terms, so a plain
-relative error is unbounded there).  The kernel is binary32 with a correctly
-rounded division, logf and erfcf; the expected error is ~1e-7 of that scale.
+relative error is unbounded there).  The kernel is binary32 with the
+hardware log2 / exp2 / reciprocal and a fitted polynomial for the normal
+tail; the expected error is ~5e-7 of that scale.
 """
 import math
 
