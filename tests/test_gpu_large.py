@@ -133,3 +133,25 @@ def test_blackscholes_past_2p31():
     err = np.abs(first.numpy().astype(np.float64) - ref) / scale[:, None]
     assert float(err.max()) <= 1e-5
     del out
+
+
+def test_batch_with_a_problem_past_2p31():
+    xv, yv = [-1.0, 0.0, 1.0], [1.0, 1.0, 0.0, -1.0]
+    x = periodic(N, xv)
+    y = periodic(N, yv)
+    small = periodic(1000, [2.0, -1.0])
+    A = torch.ones((3, 5), device=DEV)
+    v = torch.ones(5, device=DEV)
+    yg = torch.zeros(3, device=DEV)
+    banner("batch with dot n = 2^31 + 4099")
+    b = L.Batch([("dot", x, y), ("asum", small), ("gemv", 2.0, A, v, 0.0, yg), ("asum", x[1:])],
+                acc="f64combine", result_dtype=torch.float64)
+    b.run()
+    torch.cuda.synchronize()
+    prod = [xv[i % 3] * yv[i % 4] for i in range(12)]
+    assert b.results[0].item() == periodic_sum(N, prod)
+    assert b.results[1].item() == 1500.0
+    assert torch.equal(yg.cpu(), torch.full((3,), 10.0))
+    assert b.results[3].item() == periodic_sum(N - 1, [xv[(i + 1) % 3] for i in range(3)], f=abs)
+    b.close()
+    del x, y
