@@ -258,12 +258,14 @@ class Operands:
         if st != B.LIFT_OK:
             raise B.LiftError(st, f"tune {self.op}")
 
-    def time_us(self, acc, k, reps=40, trials=3):
+    def time_us(self, acc, k, reps=40, trials=5):
+        """Median over `trials` of the average time of `reps` back-to-back
+        calls that rotate over the operand sets (cold Infinity Cache)."""
         import torch
 
         for i in range(4):
             self.call(i % self.sets, acc, k)
-        best = float("inf")
+        times = []
         for _ in range(trials):
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -272,8 +274,8 @@ class Operands:
                 self.call(i % self.sets, acc, k)
             e1.record()
             torch.cuda.synchronize()
-            best = min(best, e0.elapsed_time(e1) * 1e3 / reps)
-        return best
+            times.append(e0.elapsed_time(e1) * 1e3 / reps)
+        return sorted(times)[len(times) // 2]
 
 
 def derived(op: str, storage: str, elements: int = None, n: int = None):
