@@ -42,8 +42,11 @@
  *             size, null pointer with a non-empty extent, pointer not aligned
  *             to its element size, partial overlap of an output with an
  *             input, unknown enum or knob value.  LIFT_EWORKSPACE: ws too
- *             small or null.  LIFT_EHIP: a HIP runtime call failed; its code
- *             is in lift_last_hip_error().  Nothing is enqueued on error.
+ *             small or null.  LIFT_EUNSUPPORTED: a knob combination with no
+ *             kernel instance, or a launch that would exceed the 2^32
+ *             work-items one dispatch can count (the library sizes its own
+ *             grids below that).  LIFT_EHIP: a HIP runtime call failed; its
+ *             code is in lift_last_hip_error().  Nothing is enqueued on error.
  * Determinism. For a given size, pointer alignment and knob set, the work
  *             partition and every summation order are fixed, so results are
  *             bitwise reproducible run to run.  Different knobs associate the
@@ -237,7 +240,9 @@ lift_status lift_blackscholes_ex(int64_t n, const float *s, float strike, float 
  * ((dx dx + dy dy) + dz dz)), epsilon finite, sigma > 0.  Binary32 throughout;
  * the sum over a list is split over the lanes given by lanes_per_item, in a
  * fixed order (deterministic).  LIFT_EINVAL for bad sizes, pointers or
- * parameters; n must be below 2^31. */
+ * parameters; n must be below 2^31, and n * lanes_per_item (one thread per
+ * lane of each particle) below 2^32: with the default 16 lanes, n below
+ * about 2^28. */
 lift_status lift_md(int64_t n, const float *pos, int64_t k, const int32_t *nbr, float cutoff, float epsilon,
                     float sigma, float *force, hipStream_t stream);
 

@@ -82,8 +82,14 @@ lift_status max_block(const void *kernel, int *out)
     return LIFT_OK;
 }
 
+// Work-items of one dispatch are counted in 32 bits (the dispatch packet's
+// grid size).
+constexpr int64_t MAX_DISPATCH_ITEMS = 0xFFFFFFFFLL;
+
 lift_status launch(const void *kernel, int64_t grid, int block, void *args, hipStream_t s)
 {
+    if (grid <= 0 || block <= 0 || grid * block > MAX_DISPATCH_ITEMS)
+        return LIFT_EUNSUPPORTED;
     void *argv[] = {args};
     hipError_t e;
     if (g_time_start) {
@@ -714,7 +720,7 @@ lift_status lift_scal_ex(int64_t n, float alpha, const float *x, float *out, con
     st = cu_count(&cus);
     if (st != LIFT_OK)
         return st;
-    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, INT32_MAX);
+    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, MAX_DISPATCH_ITEMS / k.block);
     const int64_t grid = std::max<int64_t>(1, (sp.nvec + chunk - 1) / chunk);
     ScalArgs a;
     a.x = x;
@@ -797,7 +803,7 @@ lift_status lift_blackscholes_ex(int64_t n, const float *s, float strike, float 
     st = cu_count(&cus);
     if (st != LIFT_OK)
         return st;
-    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, INT32_MAX);
+    const int64_t chunk = chunk_for(sp.nvec, vb / 4, k, cus, MAX_DISPATCH_ITEMS / k.block);
     BsArgs a;
     a.s = s;
     a.call_put = call_put;
@@ -843,6 +849,8 @@ lift_status lift_md_ex(int64_t n, const float *pos, int64_t k, const int32_t *nb
     if (st != LIFT_OK)
         return st;
     if (kn.vec_bytes < 4 || kn.unroll > 4)
+        return LIFT_EINVAL;
+    if (n * kn.lanes > MAX_DISPATCH_ITEMS - kn.block)  // one thread per lane of each particle
         return LIFT_EINVAL;
     if (n == 0)
         return LIFT_OK;

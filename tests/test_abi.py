@@ -278,3 +278,18 @@ def test_names_used_by_gpu_tests_and_bench_exist():
         missing += [(os.path.basename(f), n) for n in set(re.findall(r"\bL\.([A-Za-z_]\w*)", src))
                     if not hasattr(pkg, n)]
     assert not missing, missing
+
+
+# far-apart (never dereferenced) device-like addresses, so that only the size rule can reject
+_P, _N, _F = 1 << 44, 2 << 44, 3 << 44
+
+
+def test_md_rejects_more_than_2p32_work_items():
+    # one thread per lane of each particle: n x 16 (default lanes) must stay below 2^32
+    assert L.lift_md((1 << 28) + 1, _P, 4, _N, 2.5, 1.0, 1.0, _F) == L.LIFT_EINVAL
+    assert L.lift_md_ex((1 << 29) + 1, _P, 4, _N, 2.5, 1.0, 1.0, _F, B.knobs(lanes_per_item=8)) == L.LIFT_EINVAL
+
+
+@cpu_only
+def test_md_just_below_2p32_work_items_reaches_hip():
+    assert L.lift_md((1 << 28) - 64, _P, 4, _N, 2.5, 1.0, 1.0, _F) == L.LIFT_EHIP
