@@ -9,7 +9,8 @@ checks are exact; scal is compared with one binary32 multiply per element,
 and BlackScholes checks that equal prices give equal pairs at every position
 and that those pairs match the oracle.  Sizes are ragged (not a multiple of
 any vector width or step), and misaligned views exercise the scalar heads.
-About 35 GB of device memory at most; the tests free it as they go.
+About 35 GB of device memory at most (one case holds a 32 GB vector);
+the tests free it as they go.
 """
 import math
 
@@ -155,3 +156,20 @@ def test_batch_with_a_problem_past_2p31():
     assert b.results[3].item() == periodic_sum(N - 1, [xv[(i + 1) % 3] for i in range(3)], f=abs)
     b.close()
     del x, y
+
+
+def test_scal_grid_capped_below_2p32_work_items():
+    # 2^33 + 5 elements with 1024-thread work-groups of one 4-byte load each:
+    # the requested split would need 2^33 work-items; the library enlarges the
+    # chunks so one dispatch stays below 2^32, and every element is still scaled
+    n = (1 << 33) + 5
+    vals = [1.0, -2.0, 0.5, 3.0, -0.25, 8.0, 6.0]
+    x = periodic(n, vals)
+    banner("scal 2^33 + 5 in place, tiny split")
+    L.scal(2.5, x, out=x, knobs=L.knobs(block=1024, vec_bytes=4, unroll=1, split=1))
+    torch.cuda.synchronize()
+    for lo in (0, n // 3, n // 2 + 1, n - (1 << 20)):
+        got = x[lo:lo + (1 << 20)].cpu().numpy()
+        want = np.array([vals[(lo + i) % 7] * 2.5 for i in range(len(got))], dtype=np.float32)
+        assert np.array_equal(got, want), lo
+    del x
