@@ -54,6 +54,9 @@ class lift_knobs(ctypes.Structure):
 
 def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0, wg_per_cu=0, row_split=0, lanes_per_item=0,
           interleave=0):
+    """A lift_knobs struct; every field 0 selects the library's default for it
+    (interleave: LIFT_INTERLEAVE_STRIDE / LIFT_INTERLEAVE_CHUNK, 0 = default).
+    Field meanings and allowed values are those of lift_knobs in lift.h."""
     return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split, wg_per_cu, row_split, lanes_per_item,
                       interleave)
 
