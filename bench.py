@@ -23,9 +23,12 @@ Also reported on the same JSON line:
   kernels      : per-kernel average durations from back-to-back launches, and
                  median / p10 / p90 of 200 single launches timed inside their
                  dispatch, cold (rotating buffer sets) and warm (one set)
-  forms        : BlackScholes over 2^22 prices, MD (12288 and 2^20 particles), gemv fp32 (4096^2, 8192^2,
-                 16384^2), 16-bit storage (n = 2^26 asum/dot,
-                 bf16 gemv 16384^2) in each accumulation variant, as GB/s and
+  forms        : asum fp32 at n = 2^20 (50 launches replayed from one HIP
+                 graph), gemv fp32 (4096^2, 8192^2, 16384^2), 16-bit storage
+                 (n = 2^26 asum/dot, bf16 gemv 16384^2) in each accumulation
+                 variant, the batch of 4096 reductions + 256 gemv (fp32 and
+                 bf16, against the same problems per call), BlackScholes over
+                 2^22 prices, MD (12288 and 2^20 particles), as GB/s and
                  binary32-equivalent GB/s
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-forms] [--forms LIST]
