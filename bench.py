@@ -13,10 +13,12 @@ finds its operands in the 256 MB Infinity Cache.
 Also reported on the same JSON line:
   roofline     : the dominant kernel's algorithmic bytes per launch over its
                  average duration, from HIP events recorded with its dispatch
-                 (lift_time_next_launch) in every 10th step of the timed
-                 region; peak 8 TB/s; HBM traffic per launch from rocprofv3
-                 counters when they were taken on the current kernel source
-                 (else null)
+                 (lift_time_next_launch) in every 20th step of the timed
+                 region (the kernel before it in those steps carries a pair
+                 too, so the timed kernel's start is stamped after that
+                 kernel has finished); peak 8 TB/s; HBM traffic per launch
+                 from rocprofv3 counters when they were taken on the current
+                 kernel source (else null)
   cpu_baseline : the binary64 oracle on the same workload and data, in its
                  split-join form on the host cores (value) and sequentially on
                  one thread; each timed for a bounded number of seconds
@@ -95,7 +97,7 @@ def main():
                     help="forms to run: " + ", ".join(FORMS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--event-every", type=int, default=10,
+    ap.add_argument("--event-every", type=int, default=20,
                     help="time the dominant kernel in every k-th step of the timed region")
     args = ap.parse_args()
 
@@ -147,12 +149,17 @@ def main():
 
     order = ("scal", "asum", "dot")
 
-    def step(i, ev_kernel=None, ev=None, slot=None):
+    def step(i, ev_kernel=None, ev=None, slot=None, ev_prev=None):
         p = ptr[i % nsets]
-        for k in order:
-            if k == ev_kernel and slot is not None:
-                # events recorded with the kernel's own dispatch
-                st = lib.lift_time_next_launch(ev.events[2 * slot], ev.events[2 * slot + 1])
+        for j, k in enumerate(order):
+            if slot is not None and (k == ev_kernel or (ev_prev is not None and j + 1 < len(order)
+                                                        and order[j + 1] == ev_kernel)):
+                # events recorded with the kernel's own dispatch; the kernel
+                # before the timed one carries a pair too, so the timed
+                # kernel's start is recorded after that kernel has finished
+                # (otherwise the start can be stamped while it still drains)
+                evs = ev if k == ev_kernel else ev_prev
+                st = lib.lift_time_next_launch(evs.events[2 * slot], evs.events[2 * slot + 1])
                 if st != 0:
                     raise L.LiftError(st, "lift_time_next_launch")
             launch(k, p)
@@ -193,21 +200,25 @@ def main():
 
     # timed region: K steps.  In every `event_every`-th step the dominant
     # kernel is launched with HIP events recorded with its own dispatch (on
-    # the stream it runs on); timing every step would add ~5 us of idle GPU
-    # per step, so a sample is timed.
+    # the stream it runs on), and so is the kernel before it (without that,
+    # the timed kernel's start can be stamped while the previous kernel
+    # still drains, which reads ~1 us long); timing every step would add
+    # ~5 us of idle GPU per step, so a sample is timed.
     sampled = [i for i in range(args.steps) if i % args.event_every == 0]
     ev = L.HipEvents(2 * len(sampled))
+    ev_prev = L.HipEvents(2 * len(sampled))
     slot_of = {i: j for j, i in enumerate(sampled)}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        step(i, dominant, ev, slot_of.get(i))
+        step(i, dominant, ev, slot_of.get(i), ev_prev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
     durs = [ev.elapsed_ms(2 * j, 2 * j + 1) * 1e3 for j in range(len(sampled))]
     ev.close()
+    ev_prev.close()
     dom_us = sum(durs) / len(durs)
     achieved = bytes_kernel[dominant] / (dom_us * 1e-6) / 1e9
     log("timed", args.steps, "steps", f"{ms_per_step:.4f} ms/step", f"{value:.1f} GB/s",
