@@ -254,12 +254,14 @@ lift_status lift_md_ex(int64_t n, const float *pos, int64_t k, const int32_t *nb
 
 /* ---- batched form ------------------------------------------------------ */
 
-/* Many asum / dot / gemv problems of uneven size in ONE kernel launch.
- * The paper's split and map-workgroup applied to a list of problems: every
- * problem is cut into tiles (split^n), and a persistent grid of work-groups
- * takes tiles from a shared counter until none are left.  The partials of a
- * reduction are combined by whichever work-group finishes its last tile, in
- * tile order, so results do not depend on which work-group ran which tile. */
+/* Many asum / dot / gemv problems of uneven size in one run: one persistent
+ * launch over the reduction tiles and one over the gemv tiles, enqueued
+ * together (each kernel compiled for its own kind of tile).  The paper's
+ * split and map-workgroup applied to a list of problems: every problem is
+ * cut into tiles (split^n), and a persistent grid of work-groups takes tiles
+ * from a shared counter until none are left.  The partials of a reduction
+ * are combined by whichever work-group finishes its last tile, in tile
+ * order, so results do not depend on which work-group ran which tile. */
 typedef enum lift_kind {
     LIFT_KIND_ASUM = 0,
     LIFT_KIND_DOT = 1,
@@ -294,10 +296,13 @@ lift_status lift_batch_create(const lift_problem *probs, int32_t count, lift_dty
                               lift_acc acc, lift_dtype rt, const lift_knobs *knobs,
                               lift_batch **out);
 
-/* Enqueue the whole batch as one kernel on `stream`.  Allocation-free and
- * memset-free: the kernel leaves its counters reset, so the call can be
- * captured into a HIP graph and replayed.  Runs of one batch must not
- * overlap (they share the counters). */
+/* Enqueue the whole batch on `stream`: the reduction launch, then the gemv
+ * launch (either is skipped when the batch has no tiles of its kind).
+ * Allocation-free and memset-free: each kernel leaves its counters reset, so
+ * the call can be captured into a HIP graph and replayed.  Runs of one batch
+ * must not overlap (they share the counters).  An armed timing hook
+ * (lift_time_next_launch) spans the whole run: start with the first launch,
+ * stop with the last. */
 lift_status lift_batch_run(lift_batch *batch, hipStream_t stream);
 
 /* Capture lift_batch_run on `stream` (which must not be the null stream)
@@ -305,9 +310,10 @@ lift_status lift_batch_run(lift_batch *batch, hipStream_t stream);
  * hipGraphLaunch and destroys it with hipGraphExecDestroy. */
 lift_status lift_batch_capture(lift_batch *batch, hipStream_t stream, hipGraphExec_t *exec);
 
-/* Tiles in the plan, work-groups in the persistent grid, and algorithmic
- * HBM bytes of one run (each x, y, A element read once, y of gemv read
- * (beta != 0) and written, results written).  Any pointer may be NULL. */
+/* Tiles in the plan, work-groups of the run's launches together, and
+ * algorithmic HBM bytes of one run (each x, y, A element read once, y of
+ * gemv read (beta != 0) and written, results written).  Any pointer may be
+ * NULL. */
 lift_status lift_batch_info(const lift_batch *batch, int64_t *tiles, int64_t *grid, int64_t *bytes);
 
 /* Free the batch's device memory (synchronises its device).  NULL is a no-op. */

@@ -445,12 +445,12 @@ lift_status gemv_common(int64_t m, int64_t n, float alpha, int at, const void *A
     return launch(kern, grid, k.block, &a, stream);
 }
 
-const void *batch_table(int dt, int acc, int vb, int unroll)
+const void *batch_table(int dt, int acc, int vb, int unroll, bool gemv)
 {
     switch (dt) {
-    case LIFT_F32: return batch_kernel_f32(acc, vb, unroll);
-    case LIFT_BF16: return batch_kernel_bf16(acc, vb, unroll);
-    case LIFT_F16: return batch_kernel_f16(acc, vb, unroll);
+    case LIFT_F32: return batch_kernel_f32(acc, vb, unroll, gemv);
+    case LIFT_BF16: return batch_kernel_bf16(acc, vb, unroll, gemv);
+    case LIFT_F16: return batch_kernel_f16(acc, vb, unroll, gemv);
     default: return nullptr;
     }
 }
@@ -481,16 +481,19 @@ bool any_overlap(std::vector<std::pair<uintptr_t, uintptr_t>> outs,
 
 }  // namespace
 
+// A planned batch: one launch over the reduction tiles ([0]) and one over
+// the gemv tiles ([1]), each with its own tile table and counters.
 struct lift_batch {
     int device = 0;
-    int64_t ntiles = 0;
     int64_t nprobs = 0;
-    int64_t grid = 0;
     int64_t bytes = 0;
     int block = 0;
     void *dmem = nullptr;
-    const void *kern = nullptr;
-    BatchArgs args{};
+    int64_t ntiles[2] = {0, 0};
+    int64_t grid[2] = {0, 0};
+    const void *kern[2] = {nullptr, nullptr};
+    BatchArgs args[2]{};
+    hipEvent_t ev[2] = {nullptr, nullptr};  // inner ends of a timed two-launch run
 };
 
 namespace {
@@ -516,14 +519,14 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     if (k.block > 512)
         return LIFT_EUNSUPPORTED;  // built for at most 512 threads (no register spills at 8 loads in flight)
     if (k.row_split == 2)
-        return LIFT_EUNSUPPORTED;  // batch gemv tiles use one wavefront per row
+        return LIFT_EUNSUPPORTED;  // batch gemv tiles use one wavefront per row pair
     const int vb = k.vec_bytes;
     const int64_t e = vb / eb;
 
     std::vector<std::pair<uintptr_t, uintptr_t>> outs, ins;
     std::vector<BatchProblem> hp((size_t)count);
-    std::vector<BatchTile> tiles;
-    std::vector<int64_t> cost;
+    std::vector<BatchTile> tiles[2];   // reduction tiles, gemv tiles
+    std::vector<int64_t> cost[2];
     int64_t slots = 0, bytes = 0;
     const int64_t step = (int64_t)k.block * k.unroll;
     const int64_t waves = k.block / 64;
@@ -576,8 +579,8 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
                 BatchTile tl{i, (int32_t)t, t * len, std::min(len, p.nvec - t * len)};
                 if (tl.len < 0)
                     tl.len = 0;
-                tiles.push_back(tl);
-                cost.push_back(tl.len * unit_e * eb * (dot ? 2 : 1));
+                tiles[0].push_back(tl);
+                cost[0].push_back(tl.len * unit_e * eb * (dot ? 2 : 1));
             }
             bytes += q.n * eb * (dot ? 2 : 1) + rb;
         } else if (q.kind == LIFT_KIND_GEMV) {
@@ -607,8 +610,8 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
             p.ntiles = (int32_t)nt;
             for (int64_t t = 0; t < nt; ++t) {
                 BatchTile tl{i, (int32_t)t, t * rows, std::min(rows, q.m - t * rows)};
-                tiles.push_back(tl);
-                cost.push_back(tl.len * std::max<int64_t>(q.n, 1) * eb);
+                tiles[1].push_back(tl);
+                cost[1].push_back(tl.len * std::max<int64_t>(q.n, 1) * eb);
             }
             bytes += q.m * q.n * eb + q.n * 4 + q.m * 4 + (q.beta != 0.f ? q.m * 4 : 0);
         } else {
@@ -617,19 +620,24 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     }
     if (any_overlap(outs, ins))
         return LIFT_EINVAL;
-    if ((int64_t)tiles.size() > INT32_MAX || count > 0x7fffffff)
+    if ((int64_t)tiles[0].size() > INT32_MAX || (int64_t)tiles[1].size() > INT32_MAX || count > 0x7fffffff)
         return LIFT_EUNSUPPORTED;
 
-    // largest tiles first, so the dynamic schedule ends on small ones
-    std::vector<int64_t> order(tiles.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
-    std::vector<BatchTile> sorted(tiles.size());
-    for (size_t i = 0; i < order.size(); ++i)
-        sorted[i] = tiles[(size_t)order[i]];
+    // each kind's tiles largest first, so its dynamic schedule ends on small ones
+    std::vector<BatchTile> sorted[2];
+    for (int kd = 0; kd < 2; ++kd) {
+        std::vector<int64_t> order(tiles[kd].size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t x, int64_t y) { return cost[kd][x] > cost[kd][y]; });
+        sorted[kd].resize(tiles[kd].size());
+        for (size_t i = 0; i < order.size(); ++i)
+            sorted[kd][i] = tiles[kd][(size_t)order[i]];
+    }
 
-    const void *kern = batch_table(storage, acc, vb, k.unroll);
-    if (!kern)
+    const void *kern[2] = {batch_table(storage, acc, vb, k.unroll, false),
+                           batch_table(storage, acc, vb, k.unroll, true)};
+    if (!kern[0] || !kern[1])
         return LIFT_EUNSUPPORTED;
     int cus = 0;
     st = cu_count(&cus);
@@ -640,15 +648,22 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     if (he != hipSuccess)
         return hip_fail(he);
 
-    // one allocation: counters | group counters | per-problem counters |
-    // problems | tiles | slots
+    // one allocation: per launch (reductions, gemv) counters | group
+    // counters, then per-problem counters | problems | reduction tiles | gemv
+    // tiles | slots
     auto up = [](int64_t v) { return (v + 255) / 256 * 256; };
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * k.wg_per_cu, (int64_t)sorted.size()));
-    const int64_t off_gc = 256;
-    const int64_t off_pc = off_gc + up((grid + ARRIVAL_GROUP - 1) / ARRIVAL_GROUP * WS_GROUP_STRIDE);
+    int64_t grid[2], off_ct[2], off_gc[2], off = 0;
+    for (int kd = 0; kd < 2; ++kd) {
+        grid[kd] = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * k.wg_per_cu, (int64_t)sorted[kd].size()));
+        off_ct[kd] = off;
+        off_gc[kd] = off + 256;
+        off = off_gc[kd] + up((grid[kd] + ARRIVAL_GROUP - 1) / ARRIVAL_GROUP * WS_GROUP_STRIDE);
+    }
+    const int64_t off_pc = off;
     const int64_t off_pr = off_pc + up(std::max<int64_t>(count, 1) * 4);
-    const int64_t off_ti = off_pr + up(std::max<int64_t>(count, 1) * (int64_t)sizeof(BatchProblem));
-    const int64_t off_sl = off_ti + up(std::max<int64_t>((int64_t)sorted.size(), 1) * (int64_t)sizeof(BatchTile));
+    const int64_t off_ti0 = off_pr + up(std::max<int64_t>(count, 1) * (int64_t)sizeof(BatchProblem));
+    const int64_t off_ti1 = off_ti0 + up(std::max<int64_t>((int64_t)sorted[0].size(), 1) * (int64_t)sizeof(BatchTile));
+    const int64_t off_sl = off_ti1 + up(std::max<int64_t>((int64_t)sorted[1].size(), 1) * (int64_t)sizeof(BatchTile));
     const int64_t total = off_sl + std::max<int64_t>(slots, 1) * WS_SLOT;
     void *mem = nullptr;
     he = hipMalloc(&mem, (size_t)total);
@@ -658,27 +673,43 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     if ((he = hipMemset(base, 0, (size_t)off_pr)) != hipSuccess ||
         (count > 0 && (he = hipMemcpy(base + off_pr, hp.data(), hp.size() * sizeof(BatchProblem),
                                       hipMemcpyHostToDevice)) != hipSuccess) ||
-        (!sorted.empty() && (he = hipMemcpy(base + off_ti, sorted.data(), sorted.size() * sizeof(BatchTile),
-                                            hipMemcpyHostToDevice)) != hipSuccess)) {
+        (!sorted[0].empty() && (he = hipMemcpy(base + off_ti0, sorted[0].data(), sorted[0].size() * sizeof(BatchTile),
+                                               hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!sorted[1].empty() && (he = hipMemcpy(base + off_ti1, sorted[1].data(), sorted[1].size() * sizeof(BatchTile),
+                                               hipMemcpyHostToDevice)) != hipSuccess)) {
         hipFree(mem);
         return hip_fail(he);
     }
+    for (hipEvent_t &ev : b->ev) {
+        if ((he = hipEventCreate(&ev)) != hipSuccess) {
+            for (hipEvent_t &e2 : b->ev)
+                if (e2) {
+                    hipEventDestroy(e2);
+                    e2 = nullptr;
+                }
+            hipFree(mem);
+            return hip_fail(he);
+        }
+    }
     b->device = dev;
-    b->ntiles = (int64_t)sorted.size();
     b->nprobs = count;
     b->bytes = bytes;
     b->block = k.block;
-    b->grid = grid;
     b->dmem = mem;
-    b->kern = kern;
-    b->args.probs = (const BatchProblem *)(base + off_pr);
-    b->args.tiles = (const BatchTile *)(base + off_ti);
-    b->args.counters = (unsigned *)base;
-    b->args.groups = base + off_gc;
-    b->args.pcount = (unsigned *)(base + off_pc);
-    b->args.slots = base + off_sl;
-    b->args.ntiles = b->ntiles;
-    b->args.result_f64 = rt == LIFT_F64;
+    for (int kd = 0; kd < 2; ++kd) {
+        b->ntiles[kd] = (int64_t)sorted[kd].size();
+        b->grid[kd] = grid[kd];
+        b->kern[kd] = kern[kd];
+        BatchArgs &a = b->args[kd];
+        a.probs = (const BatchProblem *)(base + off_pr);
+        a.tiles = (const BatchTile *)(base + (kd == 0 ? off_ti0 : off_ti1));
+        a.counters = (unsigned *)(base + off_ct[kd]);
+        a.groups = base + off_gc[kd];
+        a.pcount = (unsigned *)(base + off_pc);
+        a.slots = base + off_sl;
+        a.ntiles = b->ntiles[kd];
+        a.result_f64 = rt == LIFT_F64;
+    }
     return LIFT_OK;
 }
 
@@ -916,7 +947,7 @@ lift_status lift_batch_run(lift_batch *b, hipStream_t stream)
 {
     if (!b)
         return LIFT_EINVAL;
-    if (b->ntiles == 0)
+    if (b->ntiles[0] + b->ntiles[1] == 0)
         return LIFT_OK;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -924,8 +955,27 @@ lift_status lift_batch_run(lift_batch *b, hipStream_t stream)
         return hip_fail(e);
     if (dev != b->device)
         return LIFT_EINVAL;
-    BatchArgs a = b->args;
-    return launch(b->kern, b->grid, b->block, &a, stream);
+    // An armed timing hook covers the whole run: its start event goes with
+    // the first launch and its stop event with the last (the batch's own
+    // pair of events fills the other ends when there are two launches).
+    const hipEvent_t t0 = g_time_start, t1 = g_time_stop;
+    g_time_start = g_time_stop = nullptr;
+    const int first = b->ntiles[0] > 0 ? 0 : 1, last = b->ntiles[1] > 0 ? 1 : 0;
+    for (int kd = first; kd <= last; ++kd) {
+        if (b->ntiles[kd] == 0)
+            continue;
+        if (t0) {
+            g_time_start = kd == first ? t0 : b->ev[1];
+            g_time_stop = kd == last ? t1 : b->ev[0];
+        }
+        BatchArgs a = b->args[kd];
+        lift_status st = launch(b->kern[kd], b->grid[kd], b->block, &a, stream);
+        if (st != LIFT_OK) {
+            g_time_start = g_time_stop = nullptr;
+            return st;
+        }
+    }
+    return LIFT_OK;
 }
 
 lift_status lift_batch_capture(lift_batch *b, hipStream_t stream, hipGraphExec_t *exec)
@@ -960,9 +1010,9 @@ lift_status lift_batch_info(const lift_batch *b, int64_t *tiles, int64_t *grid, 
     if (!b)
         return LIFT_EINVAL;
     if (tiles)
-        *tiles = b->ntiles;
+        *tiles = b->ntiles[0] + b->ntiles[1];
     if (grid)
-        *grid = b->grid;
+        *grid = (b->ntiles[0] ? b->grid[0] : 0) + (b->ntiles[1] ? b->grid[1] : 0);
     if (bytes)
         *bytes = b->bytes;
     return LIFT_OK;
@@ -974,6 +1024,9 @@ void lift_batch_destroy(lift_batch *b)
         return;
     if (b->dmem)
         hipFree(b->dmem);
+    for (hipEvent_t ev : b->ev)
+        if (ev)
+            hipEventDestroy(ev);
     delete b;
 }
 

@@ -1,22 +1,24 @@
-// Batched form: every asum / dot / gemv of a problem list in one launch.
+// Batched form: every asum / dot / gemv of a problem list in one run.
 //
 // The paper's split and map-workgroup over a list of problems.  The host cuts
 // every problem into tiles (reductions: runs of vectors; gemv: runs of rows)
-// and sorts them largest first.  A persistent grid of work-groups takes the
+// and sorts each kind's tiles largest first.  A run is two persistent
+// launches on one stream, one per kind, so that each kernel is compiled for
+// its own work (its register peak sets how many work-groups a CU holds, and
+// the reductions' need not limit the gemv's).  In each, work-groups take the
 // next tile from an agent-scope counter until the table is exhausted:
 //   reduction tile -> the per-call streaming body (lane reduce-seq, DPP wave
 //                     butterfly, LDS across waves) -> partial slot of the tile;
 //                     the work-group that finishes a problem's last tile folds
 //                     that problem's partials in tile order and writes its
 //                     result;
-//   gemv tile      -> rows that fill one step of the work-group (more than
-//                     half of it): the work-group splits each row with x held
-//                     in registers (gemv_xs_rows); other rows: each wavefront
-//                     takes pairs of rows of the tile (gemv_row_group).
+//   gemv tile      -> each wavefront takes pairs of the tile's rows
+//                     (gemv_row_group); where x fits, the work-group first
+//                     copies it into LDS and the rows read it there.
 // Tile-to-work-group assignment is dynamic, but every tile's arithmetic and
 // every combine order are fixed by the plan, so results are deterministic.
-// The last work-group to leave resets the tile counter, so the launch can be
-// replayed from a HIP graph without a memset node.
+// The last work-group to leave a launch resets that launch's counters, so a
+// run can be replayed from a HIP graph without a memset node.
 #pragma once
 
 #include "lift_gemv.hpp"
@@ -118,6 +120,30 @@ __device__ __forceinline__ void gemv_tile(const BatchProblem &p, const BatchTile
         gemv_row_group<T, ACC, VB, R, U>(p.a, x, y, end, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
 }
 
+// Rows [begin, begin + len) of a gemv problem whose x fits in `xl` (LDS):
+// the work-group copies x there once per tile, then each wavefront takes row
+// pairs as in gemv_tile, reading x from LDS instead of the cache (re-reading
+// x from the cache for every row pair limits the wavefront form; with 16-bit
+// A, x is twice A's bytes).  The arithmetic is gemv_row_group's, so both
+// forms give the same bits.  All threads of the work-group must call this
+// (it has barriers).
+template <class T, int ACC, int VB, int U>
+__device__ __forceinline__ void gemv_tile_lx(const BatchProblem &p, const BatchTile &tl, float *xl)
+{
+    constexpr int R = 2;
+    const float *x = reinterpret_cast<const float *>(p.b);
+    for (int64_t i = threadIdx.x; i < p.n; i += blockDim.x)
+        xl[i] = x[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = blockDim.x >> 6;
+    float *y = reinterpret_cast<float *>(p.out);
+    const int64_t end = tl.begin + tl.len;
+    for (int64_t r = tl.begin + (threadIdx.x >> 6) * R; r < end; r += waves * R)
+        gemv_row_group<T, ACC, VB, R, U>(p.a, xl, y, end, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
+    __syncthreads();  // every wave is done with xl before the next tile rewrites it
+}
+
 // A gemv tile whose rows one step of the work-group covers: the x-stationary
 // row-split loop of the per-call form over the tile's rows (x loaded once per
 // tile, the work-group's threads splitting each row).
@@ -167,12 +193,10 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
     using BT = typename BlockT<ACC>::type;
     using ST = typename SlotT<ACC>::type;
     constexpr int EB = T::bytes;  // element-wise loads for unaligned problems
-    constexpr bool XS_TILES = U * Elems<T, VB>::value <= 32;
     __shared__ BT lds_block[16];
     __shared__ ST lds_final[16];
     __shared__ int s_tile;
     __shared__ int s_last;
-    __shared__ RowPartT<ACC> lds_rows[2][16][16];
     const int t = threadIdx.x;
     const int64_t B = blockDim.x;
 
@@ -183,18 +207,7 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
         const int kind = __builtin_amdgcn_readfirstlane(p.kind);
         const int vec = __builtin_amdgcn_readfirstlane(p.vec);
 
-        if (kind == KIND_GEMV) {
-            // uniform: rows that fill more than half of one step keep x in
-            // registers (instances whose x slice, U x E values, fits next to
-            // the reduction path's registers); shorter rows would leave most of
-            // the work-group idle on each row, so wavefronts take row pairs
-            if (XS_TILES && vec && p.nvec * 2 > B * U && p.nvec <= B * U)
-                gemv_tile_xs<T, ACC, VB, U>(p, tl, lds_rows);
-            else if (vec)
-                gemv_tile<T, ACC, VB, U>(p, tl);
-            else
-                gemv_tile<T, ACC, EB, U>(p, tl);
-        } else {
+        {
             BT v;
             if (kind == KIND_ASUM)
                 v = vec ? tile_lane_value<T, OP_ASUM, ACC, VB, U>(p, tl) : tile_lane_value<T, OP_ASUM, ACC, EB, U>(p, tl);
@@ -235,36 +248,78 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
     }
 }
 
+// The gemv tiles of a batch: wavefronts take row pairs of each tile, reading
+// x from a copy in LDS where it fits (x of up to 4096 columns, 16 KiB), else
+// from the cache.  Same loop discipline as batch_kernel.
+template <class T, int ACC, int VB, int U>
+__global__ void __launch_bounds__(512) batch_gemv_kernel(BatchArgs a)
+{
+    constexpr int EB = T::bytes;  // element-wise loads for unaligned problems
+    constexpr int64_t LDS_X = 4096;
+    __shared__ int s_tile;
+    __shared__ __align__(16) float lds_x[LDS_X];
+    const int t = threadIdx.x;
+
+    int ti = blockIdx.x;  // the grid never exceeds the tile count
+    while (ti < a.ntiles) {
+        const BatchTile tl = a.tiles[ti];
+        const BatchProblem p = a.probs[tl.problem];
+        const int vec = __builtin_amdgcn_readfirstlane(p.vec);
+        const int in_lds = __builtin_amdgcn_readfirstlane((int)(p.n <= LDS_X));
+        if (in_lds) {
+            if (vec)
+                gemv_tile_lx<T, ACC, VB, U>(p, tl, lds_x);
+            else
+                gemv_tile_lx<T, ACC, EB, U>(p, tl, lds_x);
+        } else {
+            if (vec)
+                gemv_tile<T, ACC, VB, U>(p, tl);
+            else
+                gemv_tile<T, ACC, EB, U>(p, tl);
+        }
+        ti = fetch_tile(&a.counters[0], &s_tile);
+    }
+    if (t == 0 && arrive(&a.counters[1], a.groups)) {
+        __hip_atomic_store(&a.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Kernel tables: `gemv` picks the gemv-tile kernel, else the reduction one.
 template <class T, int ACC, int VB>
-const void *batch_pick_unroll(int unroll)
+const void *batch_pick_unroll(int unroll, bool gemv)
 {
     switch (unroll) {
-    case 1: return reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 1>);
-    case 2: return reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 2>);
-    case 4: return reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 4>);
-    case 8: return reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 8>);
+    case 1: return gemv ? reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC, VB, 1>)
+                        : reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 1>);
+    case 2: return gemv ? reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC, VB, 2>)
+                        : reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 2>);
+    case 4: return gemv ? reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC, VB, 4>)
+                        : reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 4>);
+    case 8: return gemv ? reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC, VB, 8>)
+                        : reinterpret_cast<const void *>(&batch_kernel<T, ACC, VB, 8>);
     default: return nullptr;
     }
 }
 
 template <class T, int ACC>
-const void *batch_pick_vec(int vec_bytes, int unroll)
+const void *batch_pick_vec(int vec_bytes, int unroll, bool gemv)
 {
     switch (vec_bytes) {
-    case 4: return batch_pick_unroll<T, ACC, 4>(unroll);
-    case 8: return batch_pick_unroll<T, ACC, 8>(unroll);
-    case 16: return batch_pick_unroll<T, ACC, 16>(unroll);
+    case 4: return batch_pick_unroll<T, ACC, 4>(unroll, gemv);
+    case 8: return batch_pick_unroll<T, ACC, 8>(unroll, gemv);
+    case 16: return batch_pick_unroll<T, ACC, 16>(unroll, gemv);
     default: return nullptr;
     }
 }
 
 template <class T>
-const void *pick_batch(int acc, int vec_bytes, int unroll)
+const void *pick_batch(int acc, int vec_bytes, int unroll, bool gemv)
 {
     switch (acc) {
-    case ACC_F32: return batch_pick_vec<T, ACC_F32>(vec_bytes, unroll);
-    case ACC_COMP: return batch_pick_vec<T, ACC_COMP>(vec_bytes, unroll);
-    case ACC_F64: return batch_pick_vec<T, ACC_F64>(vec_bytes, unroll);
+    case ACC_F32: return batch_pick_vec<T, ACC_F32>(vec_bytes, unroll, gemv);
+    case ACC_COMP: return batch_pick_vec<T, ACC_COMP>(vec_bytes, unroll, gemv);
+    case ACC_F64: return batch_pick_vec<T, ACC_F64>(vec_bytes, unroll, gemv);
     default: return nullptr;
     }
 }

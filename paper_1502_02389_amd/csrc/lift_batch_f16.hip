@@ -3,9 +3,9 @@
 
 namespace lift {
 
-const void *batch_kernel_f16(int acc, int vec_bytes, int unroll)
+const void *batch_kernel_f16(int acc, int vec_bytes, int unroll, bool gemv)
 {
-    return pick_batch<F16>(acc, vec_bytes, unroll);
+    return pick_batch<F16>(acc, vec_bytes, unroll, gemv);
 }
 
 }  // namespace lift

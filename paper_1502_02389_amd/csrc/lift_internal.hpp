@@ -117,9 +117,9 @@ struct BatchArgs {
     int32_t result_f64;
 };
 
-const void *batch_kernel_f32(int acc, int vec_bytes, int unroll);
-const void *batch_kernel_bf16(int acc, int vec_bytes, int unroll);
-const void *batch_kernel_f16(int acc, int vec_bytes, int unroll);
+const void *batch_kernel_f32(int acc, int vec_bytes, int unroll, bool gemv);
+const void *batch_kernel_bf16(int acc, int vec_bytes, int unroll, bool gemv);
+const void *batch_kernel_f16(int acc, int vec_bytes, int unroll, bool gemv);
 
 // Kernel tables (nullptr where a combination is not built).
 const void *reduce_kernel(int dtype, int op, int acc, int vec_bytes, int unroll);

@@ -240,10 +240,9 @@ def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
     """The batched form runs each reduction as the per-call expression with
     the batch's tiles for work-group chunks (split rounded up to whole steps,
     partials folded by the last tile's work-group like the per-call combine)
-    and each gemv row as the row expression (a work-group per row where the
-    row fills more than half of one step and fits in it and U x E <= 32,
-    else a wavefront per row; element loads where x or the rows are not
-    aligned).  Every result bit for bit."""
+    and each gemv row as the row expression of a wavefront (64 lanes, U
+    loads in flight; element loads where x or the rows are not aligned).
+    Every result bit for bit."""
     from tests import binary32 as F32B
     from tests.test_gpu_batch import build, small_spec
 
@@ -261,10 +260,7 @@ def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
             xd, yd = pr[3], pr[5]
             lda = A.shape[1]
             vec = n > 0 and (lda * eb) % vb == 0 and xd.data_ptr() % min(E * 4, 16) == 0
-            nvec = n // E if vec else n
-            xs_rows = U * E <= 32 and vec and 2 * nvec > B * U and nvec <= B * U
-            lanes = B if xs_rows else 64
-            pred = _gemv_model_rows(A, x[:n].contiguous(), y, alpha, beta, range(A.shape[0]), lanes, U,
+            pred = _gemv_model_rows(A, x[:n].contiguous(), y, alpha, beta, range(A.shape[0]), 64, U,
                                     vb if vec else eb, eb)
             got = yd.cpu().numpy()
             bad = [r for r in range(A.shape[0])
