@@ -587,7 +587,7 @@ def out_pairs(pos, nbr, cutoff, dev):
 
 
 def batch_form(L, W, dev, stream, storage):
-    """The batch of 4096 reductions + 256 gemv: one persistent launch vs per-call kernels (eager and
+    """The batch of 4096 reductions + 256 gemv: one batched run (two persistent launches) vs per-call kernels (eager and
     captured in a graph) over the same problems.  Values are drawn on the GPU
     (throughput only; parity is checked by the tests)."""
     import torch

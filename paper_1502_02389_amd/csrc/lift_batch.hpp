@@ -144,26 +144,6 @@ __device__ __forceinline__ void gemv_tile_lx(const BatchProblem &p, const BatchT
     __syncthreads();  // every wave is done with xl before the next tile rewrites it
 }
 
-// A gemv tile whose rows one step of the work-group covers: the x-stationary
-// row-split loop of the per-call form over the tile's rows (x loaded once per
-// tile, the work-group's threads splitting each row).
-template <class T, int ACC, int VB, int U>
-__device__ __forceinline__ void gemv_tile_xs(const BatchProblem &p, const BatchTile &tl,
-                                             RowPartT<ACC> (*lds)[16][16])
-{
-    GemvArgs g;
-    g.A = p.a;
-    g.x = reinterpret_cast<const float *>(p.b);
-    g.y = reinterpret_cast<float *>(p.out);
-    g.m = p.m;
-    g.n = p.n;
-    g.lda = p.lda;
-    g.nvec = p.nvec;
-    g.alpha = p.alpha;
-    g.beta = p.beta;
-    gemv_xs_rows<T, ACC, VB, 1, U>(g, tl.begin, 1, tl.begin + tl.len, lds);
-}
-
 // Next tile for the work-group: thread 0 draws it from the shared counter
 // (offset by the grid size: work-group b's first tile is b, taken without
 // an atomic, so the launch does not start with every work-group contending

@@ -109,8 +109,9 @@ struct RowAcc<ACC_COMP, E> {
     __device__ __forceinline__ Pair value() const { return p; }
 };
 
-// Largest work-group an instance is compiled for.  R x U vector loads and
-// U x E values of x are live at once; the register estimate below keeps
+// Largest work-group an instance is compiled for.  R x U vector loads,
+// U x E values of x and the R values of y read ahead are live at once; the
+// register estimate below keeps
 // every instance within the budget its launch bound grants (1024 threads:
 // 128 registers per lane, 512: 256, 256: 512) so none spills.  The host
 // reads the bound back from the kernel and lowers the work-group size to it.
@@ -120,7 +121,7 @@ constexpr int gemv_bound()
     constexpr int E = Elems<T, VB>::value;
     constexpr int load_regs = R * U * (VB < 4 ? 2 : VB / 4);  // sub-dword loads: value + address
     constexpr int acc_regs = ACC == ACC_COMP ? R * 2 + 2 * E : R * E;
-    constexpr int regs = load_regs + U * E + acc_regs;
+    constexpr int regs = load_regs + U * E + acc_regs + R;
     return regs <= 64 ? 1024 : regs <= 200 ? 512 : 256;
 }
 
@@ -129,6 +130,22 @@ __device__ __forceinline__ void store_row(float *y, int64_t i, float alpha, floa
 {
     float by = beta == 0.f ? 0.f : beta * y[i];
     y[i] = fmaf(alpha, dotv, by);
+}
+
+// The same epilogue with y_i already read (`yold`, ignored when beta is 0).
+template <int ACC>
+__device__ __forceinline__ void store_row_y(float *y, int64_t i, float alpha, float beta, float dotv, float yold)
+{
+    float by = beta == 0.f ? 0.f : beta * yold;
+    y[i] = fmaf(alpha, dotv, by);
+}
+
+// y_i of a row about to be reduced, read before the row's loads so that the
+// epilogue does not wait a dependent round trip (0 when beta is 0: y is not
+// read, as BLAS specifies, or when the row is past the end).
+__device__ __forceinline__ float prefetch_y(const float *y, int64_t i, int64_t m, float beta)
+{
+    return beta != 0.f && i < m ? y[i] : 0.f;
 }
 
 // Rows r0 .. r0 + R - 1 (clamped to m) of y = alpha * A x + beta * y, by one
@@ -146,6 +163,10 @@ __device__ __forceinline__ void gemv_row_group(const void *A, const float *x, fl
 #pragma unroll
     for (int r = 0; r < R; ++r)
         rows[r] = reinterpret_cast<const char *>(A) + min(r0 + r, m - 1) * row_bytes;
+    float yold[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        yold[r] = prefetch_y(y, r0 + r, m, beta);
 
     RowAcc<ACC, E> acc[R];
     int64_t base = 0;
@@ -216,17 +237,17 @@ __device__ __forceinline__ void gemv_row_group(const void *A, const float *x, fl
         if constexpr (ACC == ACC_F64) {
             double d = wave_sum((double)acc[r].value());
             if (lane == 0 && r0 + r < m) {
-                double by = beta == 0.f ? 0.0 : (double)beta * (double)y[r0 + r];
+                double by = beta == 0.f ? 0.0 : (double)beta * (double)yold[r];
                 y[r0 + r] = (float)((double)alpha * d + by);
             }
         } else if constexpr (ACC == ACC_COMP) {
             Pair p = wave_sum(acc[r].value());
             if (lane == 0 && r0 + r < m)
-                store_row<ACC>(y, r0 + r, alpha, beta, p.s + p.c);
+                store_row_y<ACC>(y, r0 + r, alpha, beta, p.s + p.c, yold[r]);
         } else {
             float d = wave_sum(acc[r].value());
             if (lane == 0 && r0 + r < m)
-                store_row<ACC>(y, r0 + r, alpha, beta, d);
+                store_row_y<ACC>(y, r0 + r, alpha, beta, d, yold[r]);
         }
     }
 }
@@ -257,6 +278,10 @@ __global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_split_k
 #pragma unroll
         for (int r = 0; r < R; ++r)
             rows[r] = reinterpret_cast<const char *>(a.A) + min(r0 + r, a.m - 1) * row_bytes;
+        float yold[R];  // read by wave 0, whose thread 0 stores the rows
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            yold[r] = t < 64 ? prefetch_y(a.y, r0 + r, a.m, a.beta) : 0.f;
         RowAcc<ACC, E> acc[R];
         int64_t base = 0;
         for (; base + step <= a.nvec; base += step) {
@@ -323,17 +348,17 @@ __global__ void __launch_bounds__((gemv_bound<T, ACC, VB, R, U>())) gemv_split_k
             if constexpr (ACC == ACC_F64) {
                 double d = block_sum<double>((double)acc[r].value(), lds[r]);
                 if (t == 0 && r0 + r < a.m) {
-                    double by = a.beta == 0.f ? 0.0 : (double)a.beta * (double)a.y[r0 + r];
+                    double by = a.beta == 0.f ? 0.0 : (double)a.beta * (double)yold[r];
                     a.y[r0 + r] = (float)((double)a.alpha * d + by);
                 }
             } else if constexpr (ACC == ACC_COMP) {
                 Pair p = block_sum<Pair>(acc[r].value(), lds[r]);
                 if (t == 0 && r0 + r < a.m)
-                    store_row<ACC>(a.y, r0 + r, a.alpha, a.beta, p.s + p.c);
+                    store_row_y<ACC>(a.y, r0 + r, a.alpha, a.beta, p.s + p.c, yold[r]);
             } else {
                 float d = block_sum<float>(acc[r].value(), lds[r]);
                 if (t == 0 && r0 + r < a.m)
-                    store_row<ACC>(a.y, r0 + r, a.alpha, a.beta, d);
+                    store_row_y<ACC>(a.y, r0 + r, a.alpha, a.beta, d, yold[r]);
             }
         }
     }

@@ -478,7 +478,8 @@ def gemv(alpha, A, x, beta, y, acc="f32", knobs=None, lda=None):
 
 
 class Batch:
-    """Many asum / dot / gemv problems run as one persistent kernel.
+    """Many asum / dot / gemv problems run as two persistent kernels (reduction
+    tiles, then gemv tiles) on one stream.
 
     ``problems`` is a list of tuples:
       ("asum", x)                       -> result written to a 0-d tensor
