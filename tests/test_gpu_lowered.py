@@ -207,7 +207,7 @@ def test_gemv_matches_lowered_rows_bitwise(gpu_device, case):
     assert not bad, (bad[:5], [(float(got[i]), pred[i]) for i in bad[:3]])
 
 
-@pytest.mark.parametrize("size,sample", [(4096, 128), (8192, 48)])
+@pytest.mark.parametrize("size,sample", [(4096, 128), (8192, 48), (16384, 16)])
 def test_gemv_default_launch_sampled_rows_bitwise(gpu_device, size, sample):
     """gemv fp32 at the bench's sizes through the plain entry point (library
     default launch: a work-group per row sized to it, x in registers, 8 loads
