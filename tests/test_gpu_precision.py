@@ -32,6 +32,31 @@ def vectors(request):
     return storage, x, y, ra, rd, mass
 
 
+ACC_CODE = {"f32": L.LIFT_ACC_F32, "comp": L.LIFT_ACC_F32_COMP, "f64combine": L.LIFT_ACC_F32_F64COMBINE}
+STORAGE_CODE = {"bf16": L.LIFT_BF16, "f16": L.LIFT_F16}
+
+
+@pytest.mark.parametrize("acc", ACCS)
+def test_16bit_2p26_asum_dot_library_default_launch(gpu_device, vectors, acc):
+    # the raw entry points with no knobs (the library's own launch choice),
+    # binary64 result: the call the benchmark times
+    storage, x, y, ra, rd, mass = vectors
+    banner("16-bit 2^26 library default", storage, acc)
+    xd, yd = x.to(DEV), y.to(DEV)
+    res = torch.zeros((), dtype=torch.float64, device=DEV)
+    ws = L.workspace(DEV)
+    s = torch.cuda.current_stream().cuda_stream
+    n, code = x.numel(), STORAGE_CODE[storage]
+    assert L.lift_asum_ex(n, code, xd.data_ptr(), ACC_CODE[acc], L.LIFT_F64, res.data_ptr(), ws.data_ptr(),
+                          ws.numel(), None, s) == 0
+    ga = res.item()
+    assert L.lift_dot_ex(n, code, xd.data_ptr(), yd.data_ptr(), ACC_CODE[acc], L.LIFT_F64, res.data_ptr(),
+                         ws.data_ptr(), ws.numel(), None, s) == 0
+    gd = res.item()
+    assert rel(ga, ra) <= BOUND[acc], (ga, ra)
+    assert abs(gd - rd) <= BOUND[acc] * mass, (gd, rd, mass)
+
+
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("rt", [torch.float32, torch.float64])
 def test_16bit_2p26_asum_dot(gpu_device, vectors, acc, rt):
@@ -94,12 +119,19 @@ def test_f64combine_result_carries_more_digits(gpu_device):
     assert e64 <= max(e32, 1e-7)
 
 
+@pytest.mark.parametrize("launch", ["tuned", "library default"])
 @pytest.mark.parametrize("acc", ACCS)
-def test_half_gemv_bf16(gpu_device, acc):
+def test_half_gemv_bf16(gpu_device, acc, launch):
     A, x, y, alpha, beta = _gemv_operands()
-    banner("bf16 gemv 16384", acc)
+    banner("bf16 gemv 16384", acc, launch)
     yd = y.to(DEV)
-    L.gemv(alpha, _gemv_dev(A), x.to(DEV), beta, yd, acc=acc)
+    if launch == "tuned":
+        L.gemv(alpha, _gemv_dev(A), x.to(DEV), beta, yd, acc=acc)
+    else:   # the raw entry point with no knobs: the call the benchmark times
+        size = A.shape[0]
+        xd = x.to(DEV)
+        assert L.lift_gemv_ex(size, size, alpha, L.LIFT_BF16, _gemv_dev(A).data_ptr(), size, xd.data_ptr(), beta,
+                              yd.data_ptr(), ACC_CODE[acc], None, torch.cuda.current_stream().cuda_stream) == 0
     r, mass = _gemv_ref()
     g = yd.cpu().numpy().astype(np.float64)
     err = np.abs(g - r) / mass
