@@ -111,12 +111,33 @@ def test_bitwise_deterministic(gpu_device):
         assert torch.equal(L.md(pd, nd, *params), a)
 
 
-def test_large_system_sampled(gpu_device):
+def _md_plain(pos, nbr, params):
+    """Forces through the plain entry point (the library's own launch): the
+    call the benchmark times."""
+    pd, nd = pos.to(DEV), nbr.to(DEV)
+    out = torch.empty((pos.shape[0], 4), dtype=torch.float32, device=DEV)
+    assert L.lift_md(pos.shape[0], pd.data_ptr(), nbr.shape[1], nd.data_ptr(), *params, out.data_ptr(),
+                     torch.cuda.current_stream().cuda_stream) == 0
+    return out
+
+
+def test_paper_size_system_library_default_launch(gpu_device):
+    pos, nbr, params = W.md_system()
+    banner("md 12288 particles, library default launch")
+    check(_md_plain(pos, nbr, params), pos, nbr, params)
+
+
+@pytest.mark.parametrize("launch,shuffle", [("tuned", True), ("library default", True), ("library default", False)])
+def test_large_system_sampled(gpu_device, launch, shuffle):
     import oracle
 
-    pos, nbr, params = W.md_system(W.MD_BOX_LARGE)
-    banner("md 2^20 particles")
-    f = L.md(pos.to(DEV), nbr.to(DEV), *params).cpu().numpy().astype(np.float64)
+    pos, nbr, params = W.md_system(W.MD_BOX_LARGE, shuffle=shuffle)
+    banner("md 2^20 particles", launch, "random order" if shuffle else "lattice order")
+    if launch == "tuned":
+        f = L.md(pos.to(DEV), nbr.to(DEV), *params)
+    else:
+        f = _md_plain(pos, nbr, params)
+    f = f.cpu().numpy().astype(np.float64)
     ref, mass = oracle.md(pos.numpy(), nbr.numpy(), *params, with_mass=True)
     err = np.abs(f[:, :3] - ref)
     assert np.all(err <= BAR * mass + 1e-30)
