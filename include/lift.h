@@ -261,7 +261,16 @@ lift_status lift_md_ex(int64_t n, const float *pos, int64_t k, const int32_t *nb
  * cut into tiles (split^n), and a persistent grid of work-groups takes tiles
  * from a shared counter until none are left.  The partials of a reduction
  * are combined by whichever work-group finishes its last tile, in tile
- * order, so results do not depend on which work-group ran which tile. */
+ * order, so results do not depend on which work-group ran which tile.  Each
+ * gemv row is reduced by one wavefront (its dot over 64 lanes, as in the
+ * per-call form with one row per wavefront): with vector loads where A's
+ * rows start on vec_bytes boundaries and x is aligned to
+ * min(vec_bytes / element size * 4, 16) bytes; else, for vec_bytes of at
+ * most 8, rows of at least 64 * unroll * E columns (E = vec_bytes / element
+ * size) and E copies of x, each padded to a multiple of 4 floats, fitting in
+ * 16320 floats of LDS, each row from its own start: scalars up to its first
+ * vec_bytes boundary, then vectors, then the scalar tail; else with element
+ * loads. */
 typedef enum lift_kind {
     LIFT_KIND_ASUM = 0,
     LIFT_KIND_DOT = 1,

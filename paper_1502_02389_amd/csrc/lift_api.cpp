@@ -601,7 +601,12 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
             }
             const int64_t xalign = std::min<int64_t>(e * 4, 16);
             p.vec = q.n > 0 && aligned(q.a, vb) && (q.lda * eb) % vb == 0 && aligned(q.b, xalign);
-            p.nvec = p.vec ? q.n / e : q.n;
+            // rows with heads against shifted copies of x in LDS, for rows that
+            // fill a step of the row-pair form (shorter ones keep element loads,
+            // two rows per wavefront)
+            if (!p.vec && e > 1 && vb <= 8 && q.n >= 64 * k.unroll * e && e * ((q.n + 3) / 4 * 4) <= BATCH_LDS_X)
+                p.vec = 2;
+            p.nvec = p.vec == 1 ? q.n / e : q.n;
             int64_t rows = std::max<int64_t>(1, k.split / std::max<int64_t>(1, q.n));
             rows = (rows + waves - 1) / waves * waves;
             const int64_t nt = (q.m + rows - 1) / rows;

@@ -144,6 +144,121 @@ __device__ __forceinline__ void gemv_tile_lx(const BatchProblem &p, const BatchT
     __syncthreads();  // every wave is done with xl before the next tile rewrites it
 }
 
+// Row r of a gemv problem whose rows do not all start on a VB boundary, by
+// one wavefront: a head of fewer than E columns up to the row's first
+// vector boundary, whole vectors from there (the x vectors they meet are
+// read from the copy of x shifted by the head, xl + head * stride, which
+// holds x[j + head] at j), and the scalar tail.  Lane t folds vectors t,
+// t + 64, ... as in gemv_row_group, then adds its head column (t < head) and
+// its tail column to component 0: the order of the low-level dot expression
+// with a misaligned start.  One row per wavefront (the head differs from row
+// to row), with UR loads in flight; x is read from LDS after the loads are
+// issued, so it holds no registers across their wait.
+template <class T, int ACC, int VB, int UR>
+__device__ __forceinline__ void gemv_row_skewed(const BatchProblem &p, int64_t r, const float *xl, int64_t stride,
+                                                int lane)
+{
+    constexpr int E = Elems<T, VB>::value;
+    using V = typename Vec<VB>::type;
+    float *y = reinterpret_cast<float *>(p.out);
+    const float yold = prefetch_y(y, r, p.m, p.beta);
+    const char *row = reinterpret_cast<const char *>(p.a) + r * p.lda * T::bytes;
+    const int64_t head = min((int64_t)__builtin_amdgcn_readfirstlane(
+                                 (int)(((VB - (uintptr_t)row % VB) % VB) / T::bytes)), p.n);
+    const int64_t nvec = (p.n - head) / E;
+    const int64_t tail0 = head + nvec * E;
+    const char *body = row + head * T::bytes;
+    const float *xs = xl + head * stride;
+
+    RowAcc<ACC, E> acc;
+    int64_t base = 0;
+    for (; base + 64 * UR <= nvec; base += 64 * UR) {
+        V va[UR];
+#pragma unroll
+        for (int k = 0; k < UR; ++k)
+            va[k] = load_stream<VB>(body, base + lane + 64 * k);
+        loads_in_flight();
+#pragma unroll
+        for (int k = 0; k < UR; ++k) {
+            float xf[E], af[E];
+            load_x<E>(xs, base + lane + 64 * k, xf);
+            decode<T, VB>(va[k], af);
+            acc.add(af, xf);
+        }
+    }
+    if (base < nvec) {
+        // final partial step: clamped indices keep every load in the row; the
+        // vectors past its end become zeros
+        V va[UR];
+#pragma unroll
+        for (int k = 0; k < UR; ++k)
+            va[k] = load_stream<VB>(body, min(base + lane + 64 * k, nvec - 1));
+        loads_in_flight();
+#pragma unroll
+        for (int k = 0; k < UR; ++k) {
+            const int64_t v = min(base + lane + 64 * k, nvec - 1);
+            const bool in = base + lane + 64 * k < nvec;
+            float xf[E], af[E];
+            load_x<E>(xs, v, xf);
+            decode<T, VB>(va[k], af);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                xf[e] = in ? xf[e] : 0.f;
+                af[e] = in ? af[e] : 0.f;
+            }
+            acc.add(af, xf);
+        }
+    }
+    if (lane < head)
+        acc.add_scalar(load_elem<T>(row, lane), xl[lane]);
+    if (tail0 + lane < p.n)
+        acc.add_scalar(load_elem<T>(row, tail0 + lane), xl[tail0 + lane]);
+
+    if constexpr (ACC == ACC_F64) {
+        double d = wave_sum((double)acc.value());
+        if (lane == 0) {
+            double by = p.beta == 0.f ? 0.0 : (double)p.beta * (double)yold;
+            y[r] = (float)((double)p.alpha * d + by);
+        }
+    } else if constexpr (ACC == ACC_COMP) {
+        Pair q = wave_sum(acc.value());
+        if (lane == 0)
+            store_row_y<ACC>(y, r, p.alpha, p.beta, q.s + q.c, yold);
+    } else {
+        float d = wave_sum(acc.value());
+        if (lane == 0)
+            store_row_y<ACC>(y, r, p.alpha, p.beta, d, yold);
+    }
+}
+
+// Rows [begin, begin + len) of a gemv problem with row heads (vec == 2): the
+// work-group writes the E shifted copies of x into `xl` (copy h at h *
+// stride holds x[j + h] for j < n - h), then each wavefront takes rows
+// begin + w, begin + w + W, ....  All threads of the work-group must call
+// this (it has barriers).
+template <class T, int ACC, int VB, int U>
+__device__ __forceinline__ void gemv_tile_skew(const BatchProblem &p, const BatchTile &tl, float *xl)
+{
+    constexpr int E = Elems<T, VB>::value;
+    const int64_t stride = (p.n + 3) & ~(int64_t)3;   // E * stride <= BATCH_LDS_X (planner)
+    constexpr int UR = 2 * U;   // one row per wavefront: as many bytes in flight as a row pair
+    const float *x = reinterpret_cast<const float *>(p.b);
+    for (int64_t j = threadIdx.x; j < p.n; j += blockDim.x) {
+        const float v = x[j];
+#pragma unroll
+        for (int h = 0; h < E; ++h)
+            if (j >= h)
+                xl[h * stride + j - h] = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = blockDim.x >> 6;
+    const int64_t end = tl.begin + tl.len;
+    for (int64_t r = tl.begin + (threadIdx.x >> 6); r < end; r += waves)
+        gemv_row_skewed<T, ACC, VB, UR>(p, r, xl, stride, lane);
+    __syncthreads();  // every wave is done with xl before the next tile rewrites it
+}
+
 // Next tile for the work-group: thread 0 draws it from the shared counter
 // (offset by the grid size: work-group b's first tile is b, taken without
 // an atomic, so the launch does not start with every work-group contending
@@ -229,15 +344,16 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
 }
 
 // The gemv tiles of a batch: wavefronts take row pairs of each tile, reading
-// x from a copy in LDS where it fits (x of up to 4096 columns, 16 KiB), else
-// from the cache.  Same loop discipline as batch_kernel.
+// x from a copy in LDS where it fits (up to BATCH_LDS_X columns), else from
+// the cache; rows with heads (vec == 2, vectors of at most 8 bytes) go one
+// per wavefront against shifted copies of x.  Same loop discipline as
+// batch_kernel.
 template <class T, int ACC, int VB, int U>
 __global__ void __launch_bounds__(512) batch_gemv_kernel(BatchArgs a)
 {
     constexpr int EB = T::bytes;  // element-wise loads for unaligned problems
-    constexpr int64_t LDS_X = 4096;
     __shared__ int s_tile;
-    __shared__ __align__(16) float lds_x[LDS_X];
+    __shared__ __align__(16) float lds_x[BATCH_LDS_X];
     const int t = threadIdx.x;
 
     int ti = blockIdx.x;  // the grid never exceeds the tile count
@@ -245,8 +361,11 @@ __global__ void __launch_bounds__(512) batch_gemv_kernel(BatchArgs a)
         const BatchTile tl = a.tiles[ti];
         const BatchProblem p = a.probs[tl.problem];
         const int vec = __builtin_amdgcn_readfirstlane(p.vec);
-        const int in_lds = __builtin_amdgcn_readfirstlane((int)(p.n <= LDS_X));
-        if (in_lds) {
+        const int in_lds = __builtin_amdgcn_readfirstlane((int)(p.n <= BATCH_LDS_X));
+        if (vec == 2) {
+            if constexpr (VB <= 8)   // the planner sets vec 2 only for these widths
+                gemv_tile_skew<T, ACC, VB, U>(p, tl, lds_x);
+        } else if (in_lds) {
             if (vec)
                 gemv_tile_lx<T, ACC, VB, U>(p, tl, lds_x);
             else

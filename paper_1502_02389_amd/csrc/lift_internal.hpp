@@ -73,10 +73,12 @@ enum Kind { KIND_ASUM = 0, KIND_DOT = 1, KIND_GEMV = 2 };
 // One problem of a batch, as the kernel reads it.  Reductions: the element
 // range is head scalars, nvec vectors of the batch's vector width (or, when
 // vec == 0, nvec = n single elements), then the scalar tail.  gemv: rows of
-// lda elements, nvec vectors per row when vec != 0.
+// lda elements, nvec vectors per row when vec == 1; vec == 2: rows whose
+// starts fall inside a vector, each read as a scalar head, whole vectors and
+// a scalar tail, against copies of x in LDS shifted by the head.
 struct BatchProblem {
     int32_t kind;
-    int32_t vec;        // 1: vector loads; 0: element loads
+    int32_t vec;        // 1: vector loads; 0: element loads; 2: gemv rows with heads
     int32_t ntiles;
     int32_t pad;
     int64_t n;          // elements (reductions) or columns (gemv)
@@ -91,6 +93,12 @@ struct BatchProblem {
     float alpha;
     float beta;
 };
+
+// Floats of x that a batch gemv work-group holds in LDS: one copy (rows of at
+// most this many columns), or, for rows with heads, E = vector width / element
+// size copies shifted by 0 .. E - 1 elements, each padded to a multiple of 4
+// floats.  64 KiB with the work-group's other LDS.
+constexpr int64_t BATCH_LDS_X = 16320;
 
 // One tile: vectors (or elements) [begin, begin + len) of a reduction, or
 // rows [begin, begin + len) of a gemv.

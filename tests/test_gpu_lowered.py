@@ -21,6 +21,7 @@ from tests.gpu_util import banner, o_asum, o_dot, rel
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 EB = {"f32": 4, "bf16": 2, "f16": 2}
+BATCH_LDS_X = 16320   # floats of LDS for copies of x in the batched form's gemv tiles (include/lift.h)
 F32 = dict(add=lambda a, b: np.float32(a) + np.float32(b), absval=lambda a: np.float32(abs(a)),
            zero=np.float32(0))
 
@@ -174,11 +175,12 @@ GEMV_CASES = [
 ]
 
 
-def _gemv_model_rows(A, x, y, alpha, beta, rows, lanes, unroll, vec_bytes, eb):
+def _gemv_model_rows(A, x, y, alpha, beta, rows, lanes, unroll, vec_bytes, eb, misalign_elems=0):
     from tests import binary32 as F32B
 
     n = x.numel()
-    shape = LW.launch_shape(n, eb, vec_bytes, lanes, unroll, max(n, 1))     # one chunk: the whole row
+    shape = LW.launch_shape(n, eb, vec_bytes, lanes, unroll, max(n, 1),    # one chunk: the whole row
+                            misalign_elems=misalign_elems)
     xs = [float(v) for v in x.numpy()]
     Af = A.float().numpy()
     return LW.evaluate_gemv_rows([[float(v) for v in Af[i, :n]] for i in rows], xs, float(alpha), float(beta),
@@ -241,7 +243,10 @@ def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
     the batch's tiles for work-group chunks (split rounded up to whole steps,
     partials folded by the last tile's work-group like the per-call combine)
     and each gemv row as the row expression of a wavefront (64 lanes, U
-    loads in flight; element loads where x or the rows are not aligned).
+    loads in flight); where the rows do not all start on a vector boundary
+    (or x is not aligned), each row from its own start, with a scalar head
+    up to its first boundary (vectors of at most 8 bytes, rows filling a
+    step, x copies fitting in LDS), else element loads.
     Every result bit for bit."""
     from tests import binary32 as F32B
     from tests.test_gpu_batch import build, small_spec
@@ -259,9 +264,22 @@ def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
             alpha, A, x, beta, y, n = item[1]
             xd, yd = pr[3], pr[5]
             lda = A.shape[1]
-            vec = n > 0 and (lda * eb) % vb == 0 and xd.data_ptr() % min(E * 4, 16) == 0
-            pred = _gemv_model_rows(A, x[:n].contiguous(), y, alpha, beta, range(A.shape[0]), 64, U,
-                                    vb if vec else eb, eb)
+            ad = pr[2].data_ptr()
+            vec = n > 0 and ad % vb == 0 and (lda * eb) % vb == 0 and xd.data_ptr() % min(E * 4, 16) == 0
+            heads = not vec and E > 1 and vb <= 8 and n >= 64 * U * E and E * (-(-n // 4) * 4) <= BATCH_LDS_X
+            if heads:
+                # each row from its own start: a head up to its first vector boundary
+                pred = [None] * A.shape[0]
+                by_mis = {}
+                for r in range(A.shape[0]):
+                    by_mis.setdefault(((ad + r * lda * eb) % vb) // eb, []).append(r)
+                for mis, rows in by_mis.items():
+                    for r, v in zip(rows, _gemv_model_rows(A, x[:n].contiguous(), y, alpha, beta, rows, 64, U,
+                                                           vb, eb, misalign_elems=mis)):
+                        pred[r] = v
+            else:
+                pred = _gemv_model_rows(A, x[:n].contiguous(), y, alpha, beta, range(A.shape[0]), 64, U,
+                                        vb if vec else eb, eb)
             got = yd.cpu().numpy()
             bad = [r for r in range(A.shape[0])
                    if np.float32(got[r]).view(np.uint32) != np.float32(pred[r]).view(np.uint32)]
