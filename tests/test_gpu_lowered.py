@@ -301,3 +301,45 @@ def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
             got = b.results[i].item()
             assert np.float32(got).view(np.uint32) == np.float32(pred).view(np.uint32), (i, kind, n, got, pred)
     b.close()
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16", "f32"])
+def test_batch_gemv_row_heads_bitwise(gpu_device, storage):
+    """gemv rows that start inside a vector (row pitch not a multiple of the
+    8-byte vector, or x misaligned), long enough for the head form: every
+    head length occurs, and each row matches the row expression of 64 lanes
+    with its own misaligned start, bit for bit."""
+    from tests.test_gpu_batch import _dev_copy
+
+    kn = dict(block=512, vec_bytes=8, unroll=4, split=262144, wg_per_cu=8)
+    eb, vb, U = EB[storage], 8, 4
+    E = vb // eb
+    g = W.gen(77)
+    cases = []          # (A on the CPU, x, y, device A, device x, device y, alpha, beta)
+    for j, (m, n) in enumerate([(37, 64 * U * E + 1), (29, 64 * U * E + 3), (23, 64 * U * E + 5), (19, 2047),
+                                (17, 64 * U * E)]):
+        A = W.normal((m, n), g, storage)
+        x = W.normal(n, g)
+        y = W.normal(m, g)
+        xd = _dev_copy(x, 1 if j == 4 else 0)     # the last: aligned rows, misaligned x
+        cases.append((A, x, y, A.to(DEV), xd, y.to(DEV), 1.25, 0.5 if j % 2 == 0 else 0.0))
+    problems = [("gemv", a, Ad, xd, b, yd) for (_, _, _, Ad, xd, yd, a, b) in cases]
+    banner("batch gemv row heads", storage)
+    b = L.Batch(problems, knobs=L.knobs(**kn))
+    b.run()
+    torch.cuda.synchronize()
+    for (A, x, y, Ad, xd, yd, alpha, beta) in cases:
+        m, n = A.shape
+        ad = Ad.data_ptr()
+        assert (n * eb) % vb != 0 or xd.data_ptr() % 16 != 0      # every case takes the head form
+        got = yd.cpu().numpy()
+        by_mis = {}
+        for r in range(m):
+            by_mis.setdefault(((ad + r * n * eb) % vb) // eb, []).append(r)
+        if storage != "f32":
+            assert len(by_mis) == E or n % E == 0            # all head lengths occur when the pitch is odd
+        for mis, rows in by_mis.items():
+            pred = _gemv_model_rows(A, x, y, alpha, beta, rows, 64, U, vb, eb, misalign_elems=mis)
+            bad = [r for r, p in zip(rows, pred) if np.float32(got[r]).view(np.uint32) != np.float32(p).view(np.uint32)]
+            assert not bad, (storage, m, n, mis, bad[:4])
+    b.close()
