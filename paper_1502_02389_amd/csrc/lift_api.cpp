@@ -608,6 +608,10 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
                 p.vec = 2;
             p.nvec = p.vec == 1 ? q.n / e : q.n;
             int64_t rows = std::max<int64_t>(1, k.split / std::max<int64_t>(1, q.n));
+            // a wavefront pays a memory round trip per row pair whatever the
+            // rows' length: at most 16 row pairs per wavefront in a tile, so
+            // short rows spread over many work-groups
+            rows = std::min<int64_t>(rows, waves * 2 * 16);
             rows = (rows + waves - 1) / waves * waves;
             const int64_t nt = (q.m + rows - 1) / rows;
             if (nt > INT32_MAX)
@@ -616,7 +620,8 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
             for (int64_t t = 0; t < nt; ++t) {
                 BatchTile tl{i, (int32_t)t, t * rows, std::min(rows, q.m - t * rows)};
                 tiles[1].push_back(tl);
-                cost[1].push_back(tl.len * std::max<int64_t>(q.n, 1) * eb);
+                // a row shorter than one step of loads costs about a whole step
+                cost[1].push_back(tl.len * std::max<int64_t>(q.n, 64 * k.unroll * e) * eb);
             }
             bytes += q.m * q.n * eb + q.n * 4 + q.m * 4 + (q.beta != 0.f ? q.m * 4 : 0);
         } else {
