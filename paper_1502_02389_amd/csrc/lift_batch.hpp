@@ -144,104 +144,128 @@ __device__ __forceinline__ void gemv_tile_lx(const BatchProblem &p, const BatchT
     __syncthreads();  // every wave is done with xl before the next tile rewrites it
 }
 
-// Row r of a gemv problem whose rows do not all start on a VB boundary, by
-// one wavefront: a head of fewer than E columns up to the row's first
-// vector boundary, whole vectors from there (the x vectors they meet are
-// read from the copy of x shifted by the head, xl + head * stride, which
-// holds x[j + head] at j), and the scalar tail.  Lane t folds vectors t,
-// t + 64, ... as in gemv_row_group, then adds its head column (t < head) and
-// its tail column to component 0: the order of the low-level dot expression
-// with a misaligned start.  One row per wavefront (the head differs from row
-// to row), with UR loads in flight; x is read from LDS after the loads are
-// issued, so it holds no registers across their wait.
-template <class T, int ACC, int VB, int UR>
-__device__ __forceinline__ void gemv_row_skewed(const BatchProblem &p, int64_t r, const float *xl, int64_t stride,
-                                                int lane)
+// Rows r0 .. r0 + R - 1 of a gemv problem whose rows do not all start on a
+// VB boundary, by one wavefront (rows from `end` on are read at a clamped
+// index and not written).  Each row has its own head of fewer than E
+// columns up to its first vector boundary, whole vectors from there (the x
+// vectors they meet are read from the copy of x shifted by that head, xl +
+// head * stride, which holds x[j + head] at j), and its scalar tail.  Lane
+// t folds vectors t, t + 64, ... of each row as in gemv_row_group, then
+// adds its head column (t < head) and its tail column to component 0: the
+// order of the low-level dot expression with a misaligned start, row by
+// row.  The rows' vector counts may differ by one; x is read from LDS after
+// the loads are issued, so it holds no registers across their wait.
+template <class T, int ACC, int VB, int R, int UR>
+__device__ __forceinline__ void gemv_rows_skewed(const BatchProblem &p, int64_t r0, int64_t end, const float *xl,
+                                                 int64_t stride, int lane)
 {
     constexpr int E = Elems<T, VB>::value;
     using V = typename Vec<VB>::type;
     float *y = reinterpret_cast<float *>(p.out);
-    const float yold = prefetch_y(y, r, p.m, p.beta);
-    const char *row = reinterpret_cast<const char *>(p.a) + r * p.lda * T::bytes;
-    const int64_t head = min((int64_t)__builtin_amdgcn_readfirstlane(
-                                 (int)(((VB - (uintptr_t)row % VB) % VB) / T::bytes)), p.n);
-    const int64_t nvec = (p.n - head) / E;
-    const int64_t tail0 = head + nvec * E;
-    const char *body = row + head * T::bytes;
-    const float *xs = xl + head * stride;
+    const char *row[R], *body[R];
+    const float *xs[R];
+    int64_t head[R], nvec[R];
+    float yold[R];
+    int64_t nmin = INT64_MAX;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        yold[r] = prefetch_y(y, r0 + r, end, p.beta);
+        row[r] = reinterpret_cast<const char *>(p.a) + min(r0 + r, end - 1) * p.lda * T::bytes;
+        head[r] = min((int64_t)__builtin_amdgcn_readfirstlane(
+                          (int)(((VB - (uintptr_t)row[r] % VB) % VB) / T::bytes)), p.n);
+        nvec[r] = (p.n - head[r]) / E;
+        nmin = min(nmin, nvec[r]);
+        body[r] = row[r] + head[r] * T::bytes;
+        xs[r] = xl + head[r] * stride;
+    }
 
-    RowAcc<ACC, E> acc;
+    RowAcc<ACC, E> acc[R];
     int64_t base = 0;
-    for (; base + 64 * UR <= nvec; base += 64 * UR) {
-        V va[UR];
+    for (; base + 64 * UR <= nmin; base += 64 * UR) {
+        V va[R][UR];
 #pragma unroll
-        for (int k = 0; k < UR; ++k)
-            va[k] = load_stream<VB>(body, base + lane + 64 * k);
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < UR; ++k)
+                va[r][k] = load_stream<VB>(body[r], base + lane + 64 * k);
         loads_in_flight();
 #pragma unroll
-        for (int k = 0; k < UR; ++k) {
-            float xf[E], af[E];
-            load_x<E>(xs, base + lane + 64 * k, xf);
-            decode<T, VB>(va[k], af);
-            acc.add(af, xf);
-        }
-    }
-    if (base < nvec) {
-        // final partial step: clamped indices keep every load in the row; the
-        // vectors past its end become zeros
-        V va[UR];
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int k = 0; k < UR; ++k)
-            va[k] = load_stream<VB>(body, min(base + lane + 64 * k, nvec - 1));
-        loads_in_flight();
-#pragma unroll
-        for (int k = 0; k < UR; ++k) {
-            const int64_t v = min(base + lane + 64 * k, nvec - 1);
-            const bool in = base + lane + 64 * k < nvec;
-            float xf[E], af[E];
-            load_x<E>(xs, v, xf);
-            decode<T, VB>(va[k], af);
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                xf[e] = in ? xf[e] : 0.f;
-                af[e] = in ? af[e] : 0.f;
+            for (int k = 0; k < UR; ++k) {
+                float xf[E], af[E];
+                load_x<E>(xs[r], base + lane + 64 * k, xf);
+                decode<T, VB>(va[r][k], af);
+                acc[r].add(af, xf);
             }
-            acc.add(af, xf);
-        }
     }
-    if (lane < head)
-        acc.add_scalar(load_elem<T>(row, lane), xl[lane]);
-    if (tail0 + lane < p.n)
-        acc.add_scalar(load_elem<T>(row, tail0 + lane), xl[tail0 + lane]);
+    // the rest of every row (vector counts may differ by one, so a row may
+    // need a last step the other does not): clamped indices keep every load
+    // in its row; the vectors past a row's end become zeros
+    for (; base < nvec[0] || (R > 1 && base < nvec[R - 1]); base += 64 * UR) {
+        V va[R][UR];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < UR; ++k)
+                va[r][k] = load_stream<VB>(body[r], max(min(base + lane + 64 * k, nvec[r] - 1), (int64_t)0));
+        loads_in_flight();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < UR; ++k) {
+                const int64_t v = max(min(base + lane + 64 * k, nvec[r] - 1), (int64_t)0);
+                const bool in = base + lane + 64 * k < nvec[r];
+                float xf[E], af[E];
+                load_x<E>(xs[r], v, xf);
+                decode<T, VB>(va[r][k], af);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    xf[e] = in ? xf[e] : 0.f;
+                    af[e] = in ? af[e] : 0.f;
+                }
+                acc[r].add(af, xf);
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (lane < head[r])
+            acc[r].add_scalar(load_elem<T>(row[r], lane), xl[lane]);
+        const int64_t tail0 = head[r] + nvec[r] * E;
+        if (tail0 + lane < p.n)
+            acc[r].add_scalar(load_elem<T>(row[r], tail0 + lane), xl[tail0 + lane]);
+    }
 
-    if constexpr (ACC == ACC_F64) {
-        double d = wave_sum((double)acc.value());
-        if (lane == 0) {
-            double by = p.beta == 0.f ? 0.0 : (double)p.beta * (double)yold;
-            y[r] = (float)((double)p.alpha * d + by);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if constexpr (ACC == ACC_F64) {
+            double d = wave_sum((double)acc[r].value());
+            if (lane == 0 && r0 + r < end) {
+                double by = p.beta == 0.f ? 0.0 : (double)p.beta * (double)yold[r];
+                y[r0 + r] = (float)((double)p.alpha * d + by);
+            }
+        } else if constexpr (ACC == ACC_COMP) {
+            Pair q = wave_sum(acc[r].value());
+            if (lane == 0 && r0 + r < end)
+                store_row_y<ACC>(y, r0 + r, p.alpha, p.beta, q.s + q.c, yold[r]);
+        } else {
+            float d = wave_sum(acc[r].value());
+            if (lane == 0 && r0 + r < end)
+                store_row_y<ACC>(y, r0 + r, p.alpha, p.beta, d, yold[r]);
         }
-    } else if constexpr (ACC == ACC_COMP) {
-        Pair q = wave_sum(acc.value());
-        if (lane == 0)
-            store_row_y<ACC>(y, r, p.alpha, p.beta, q.s + q.c, yold);
-    } else {
-        float d = wave_sum(acc.value());
-        if (lane == 0)
-            store_row_y<ACC>(y, r, p.alpha, p.beta, d, yold);
     }
 }
 
 // Rows [begin, begin + len) of a gemv problem with row heads (vec == 2): the
 // work-group writes the E shifted copies of x into `xl` (copy h at h *
-// stride holds x[j + h] for j < n - h), then each wavefront takes rows
-// begin + w, begin + w + W, ....  All threads of the work-group must call
-// this (it has barriers).
+// stride holds x[j + h] for j < n - h), then each wavefront takes row
+// pairs begin + 2w, begin + 2w + 2W, ....  All threads of the work-group
+// must call this (it has barriers).
 template <class T, int ACC, int VB, int U>
 __device__ __forceinline__ void gemv_tile_skew(const BatchProblem &p, const BatchTile &tl, float *xl)
 {
     constexpr int E = Elems<T, VB>::value;
     const int64_t stride = (p.n + 3) & ~(int64_t)3;   // E * stride <= BATCH_LDS_X (planner)
-    constexpr int UR = 2 * U;   // one row per wavefront: as many bytes in flight as a row pair
     const float *x = reinterpret_cast<const float *>(p.b);
     for (int64_t j = threadIdx.x; j < p.n; j += blockDim.x) {
         const float v = x[j];
@@ -254,8 +278,8 @@ __device__ __forceinline__ void gemv_tile_skew(const BatchProblem &p, const Batc
     const int lane = threadIdx.x & 63;
     const int64_t waves = blockDim.x >> 6;
     const int64_t end = tl.begin + tl.len;
-    for (int64_t r = tl.begin + (threadIdx.x >> 6); r < end; r += waves)
-        gemv_row_skewed<T, ACC, VB, UR>(p, r, xl, stride, lane);
+    for (int64_t r = tl.begin + (threadIdx.x >> 6) * 2; r < end; r += waves * 2)
+        gemv_rows_skewed<T, ACC, VB, 2, U>(p, r, end, xl, stride, lane);
     __syncthreads();  // every wave is done with xl before the next tile rewrites it
 }
 
