@@ -236,8 +236,12 @@ lift_status lift_blackscholes_ex(int64_t n, const float *s, float strike, float 
  *        e.g. with -1).  A particle must not list itself.
  * force: n x 4 floats (fx, fy, fz, 0), 16-byte aligned, not overlapping pos
  *        or nbr.
- * cutoff >= 0 (the test is r^2 < binary32(cutoff^2), taken in binary32 on
- * ((dx dx + dy dy) + dz dz)), epsilon finite, sigma > 0.  Binary32 throughout;
+ * cutoff >= 0: the test is r^2 < binary32(cutoff^2), taken in binary32 on
+ * ((dx dx + dy dy) + dz dz) without contraction, which agrees with the exact
+ * |p - q| < cutoff for every pair whose squared distance is more than 6
+ * binary32 ulps (relative 6 * 2^-24) from cutoff^2; nearer pairs may fall
+ * either way, the same way on every call.  epsilon finite, sigma > 0.
+ * Binary32 throughout;
  * the sum over a list is split over the lanes given by lanes_per_item, in a
  * fixed order (deterministic).  LIFT_EINVAL for bad sizes, pointers or
  * parameters; n must be below 2^31, and n * lanes_per_item (one thread per

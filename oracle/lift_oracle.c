@@ -545,23 +545,21 @@ int oracle_blackscholes(int64_t n, int st, const void *s, double strike, double 
  *   - positions are 4 floats per particle (x, y, z, unused), forces 3 values;
  *   - N is an n x k row-major matrix of int32 indices; an index outside
  *     [0, n) is an empty slot and leaves f unchanged (lists of uneven length);
- *   - "d < t" is taken as r^2 < t^2, and this decision (an integer outcome
- *     decided by floating point) is taken in binary32 exactly as the GPU
- *     kernel takes it: differences and ((dx dx + dy dy) + dz dz) in binary32
- *     without contraction, compared with t2 = binary32(t * t).  The force is
- *     then evaluated in binary64 from the stored binary32 positions;
+ *   - "d < t" is the plain definition: the Euclidean distance of the two
+ *     stored binary32 positions, evaluated in binary64 (the differences are
+ *     exact there, the distance is within a few binary64 ulps), compared
+ *     with t.  The force is evaluated in binary64 from the same positions;
  *   - reduce is the sequential fold over the list in order (the fused lambda
  *     is valid only for reduce-seq).
  */
 typedef struct { double x, y, z; } vec3_t;
-typedef struct { double eps24, sigma2; float t2; } md_params;
+typedef struct { double eps24, sigma2, t; } md_params;
 
-static int md_within(const float *p, const float *q, float t2)
+/* updateF's test: distance(p, q) < t */
+static int md_within(const float *p, const float *q, double t)
 {
-    volatile float dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
-    volatile float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-    volatile float r2 = (xx + yy) + zz;
-    return r2 < t2;
+    double d0 = (double)p[0] - q[0], d1 = (double)p[1] - q[1], d2 = (double)p[2] - q[2];
+    return sqrt(d0 * d0 + d1 * d1 + d2 * d2) < t;
 }
 
 /* calculateForce: the pair force on p from q (binary64 from binary32 input) */
@@ -588,7 +586,7 @@ static vec3_t update_f(vec3_t f, int32_t nid, const float *p, const float *ps, i
     if (nid < 0 || (int64_t)nid >= n)
         return f;  /* empty slot */
     const float *q = ps + 4 * (int64_t)nid;
-    if (md_within(p, q, m->t2)) {
+    if (md_within(p, q, m->t)) {
         vec3_t g = calculate_force(p, q, m, mass);
         f.x += g.x;
         f.y += g.y;
@@ -604,7 +602,7 @@ int oracle_md(int64_t n, const float *pos, int64_t k, const int32_t *nbr, double
         return OR_EINVAL;
     if (!(cutoff >= 0) || !isfinite(cutoff) || !(sigma > 0) || !isfinite(sigma) || !isfinite(epsilon))
         return OR_EINVAL;
-    md_params m = {24.0 * epsilon, sigma * sigma, (float)(cutoff * cutoff)};
+    md_params m = {24.0 * epsilon, sigma * sigma, cutoff};
     for (int64_t i = 0; i < n; ++i) {  /* map over zip(ps, N) */
         const float *p = pos + 4 * i;
         vec3_t f = {0.0, 0.0, 0.0};    /* reduce(..., 0, ns): fold in list order */

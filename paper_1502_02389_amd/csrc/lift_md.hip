@@ -16,8 +16,11 @@
 // outside [0, n)) load nothing and contribute zero.
 //
 // Per neighbour, in binary32: d = p - q, r2 = (dx dx + dy dy) + dz dz
-// (no contraction: the cutoff test r2 < t^2 is an exact, reproducible
-// decision), then 1/r2 by the hardware reciprocal, s6 = (sigma^2 / r2)^3,
+// without contraction, and the cutoff test r2 < binary32(t^2).  That r2 is
+// within about 5 ulps of the exact squared distance, so the test agrees
+// with "distance < t" except for pairs whose squared distance lies within
+// about 6 binary32 ulps of t^2; it is the same decision on every run and
+// knob point.  Then 1/r2 by the hardware reciprocal, s6 = (sigma^2 / r2)^3,
 // f = 24 eps / r2 * s6 * (2 s6 - 1) (zero outside the cutoff) and F += f d
 // by fma.
 #include "lift_device.hpp"

@@ -1,11 +1,17 @@
 """GPU parity of MD (Fig. 7): forces from neighbour lists, Lennard-Jones.
 
-Both sides take the cutoff decision in binary32 the same way, so the set of
-interacting pairs is identical; the forces are then held to 1e-5 of the
-magnitude of their terms, per particle and component (sum over the
-interacting neighbours of |repulsive| + |attractive| times |d|: the sum of
-the forces cancels, so a plain relative error is unbounded).
+The oracle decides updateF's test "distance < t" exactly (binary64 on the
+stored positions); the kernel decides r^2 < binary32(t^2) on a binary32
+r^2.  The two can differ only for pairs whose squared distance lies within
+the kernel's rounding of t^2 (R2_BAND below), so every such pair is found in
+binary64 and its term is allowed either way; every other pair must be
+decided alike.  Forces are held to 1e-5 of the magnitude of their terms,
+per particle and component (sum over the interacting neighbours of
+|repulsive| + |attractive| times |d|: the sum of the forces cancels, so a
+plain relative error is unbounded).
 """
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -17,17 +23,72 @@ from tests.gpu_util import banner
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 BAR = 1e-5
+# The kernel's r^2 = (dx dx + dy dy) + dz dz in binary32 from rounded
+# differences is within (1 + u)^5 - 1 ~ 5u of the exact r^2 (u = 2^-24: one
+# rounding per difference, squared, one per square, two additions), and
+# binary32(t^2) within u of t^2; 8u leaves room for second-order terms.
+R2_BAND = 8 * 2.0 ** -24
+
+
+def borderline_pairs(pos, nbr, cutoff):
+    """Listed (particle, neighbour) pairs whose binary64 squared distance lies
+    within R2_BAND * t^2 of t^2: the only pairs the kernel may decide
+    differently from the exact test."""
+    p = pos[:, :3].astype(np.float64)
+    n, k = nbr.shape
+    t2 = float(cutoff) ** 2
+    found = {}
+    step = max(1, (1 << 22) // max(k, 1))
+    for lo in range(0, n if k else 0, step):
+        idx = nbr[lo:lo + step]
+        valid = (idx >= 0) & (idx < n)
+        d = p[lo:lo + len(idx), None, :] - p[np.where(valid, idx, 0)]
+        r2 = (d * d).sum(-1)
+        for a, b in zip(*np.nonzero(valid & (np.abs(r2 - t2) <= R2_BAND * t2))):
+            found.setdefault(lo + int(a), []).append(int(idx[a, b]))
+    return found
+
+
+def pair_term(pos, i, j, params):
+    """The oracle's term of neighbour j in particle i's force (decided by the
+    oracle's own test), the term itself, and its magnitude."""
+    import oracle
+
+    two = np.ascontiguousarray(pos[[i, j]])
+    nb = np.array([[1], [-1]], np.int32)
+    cutoff, eps, sigma = params
+    f, m = oracle.md(two, nb, 1e30, eps, sigma, with_mass=True)
+    inside = bool(np.any(oracle.md(two, nb, cutoff, eps, sigma)[0] != 0.0))
+    return inside, f[0], m[0]
 
 
 def check(got, pos, nbr, params):
     import oracle
 
-    ref, mass = oracle.md(pos.numpy(), nbr.numpy(), *params, with_mass=True)
+    pos_np, nbr_np = pos.numpy(), nbr.numpy()
+    ref, mass = oracle.md(pos_np, nbr_np, *params, with_mass=True)
     g = got.cpu().numpy().astype(np.float64)
     assert np.all(g[:, 3] == 0.0)
     err = np.abs(g[:, :3] - ref)
-    bad = err > BAR * mass + 1e-30
-    assert not bad.any(), (int(bad.sum()), float((err / np.maximum(mass, 1e-30)).max()))
+    bad = np.nonzero((err > BAR * mass + 1e-30).any(1))[0]
+    border = borderline_pairs(pos_np, nbr_np, params[0]) if len(bad) else {}
+    for i in bad:
+        # only a particle with pairs at the cutoff may differ, and only by
+        # some of those pairs' terms, each counted in or out
+        assert i in border, (int(i), float((err[i] / np.maximum(mass[i], 1e-30)).max()))
+        terms = [pair_term(pos_np, i, j, params) for j in border[i]]
+        assert len(terms) <= 8, (int(i), len(terms))
+        ok = False
+        for flips in itertools.product((False, True), repeat=len(terms)):
+            adj, m = ref[i].copy(), mass[i].copy()
+            for flip, (inside, f, fm) in zip(flips, terms):
+                if flip:
+                    adj += -f if inside else f
+                    m += fm
+            if np.all(np.abs(g[i, :3] - adj) <= BAR * m + 1e-30):
+                ok = True
+                break
+        assert ok, (int(i), border[i])
     return ref
 
 
@@ -87,20 +148,43 @@ def test_empty_slots_and_degenerate_sizes(gpu_device):
                 *params).shape == (0, 4)
 
 
-def test_cutoff_boundary_decided_like_the_oracle(gpu_device):
-    # pairs placed exactly at and just inside the cutoff
+def test_cutoff_boundary(gpu_device):
+    # pairs at exactly t, 1 ulp inside and 1 ulp outside (both within the
+    # kernel's band: either decision is allowed, the force must be one of
+    # the two), and pairs 64 ulps inside and outside, which the kernel must
+    # decide as the exact test does
     t = 1.25
-    pos = torch.zeros((4, 4))
-    pos[1, 0] = t
-    pos[3, 0] = float(np.nextafter(np.float32(t), np.float32(0)))
-    pos[2, 1] = 3.0
-    pos[3, 1] = 3.0
-    nbr = torch.tensor([[1], [0], [3], [2]], dtype=torch.int32)
+    tf = np.float32(t)
+    seps = [tf, np.nextafter(tf, np.float32(0)), np.nextafter(tf, np.float32(2)),
+            np.float32(t * (1 - 64 * 2.0 ** -24)), np.float32(t * (1 + 64 * 2.0 ** -24))]
+    pos = torch.zeros((2 * len(seps), 4))
+    for c, sep in enumerate(seps):
+        pos[2 * c, 1] = pos[2 * c + 1, 1] = 3.0 * c
+        pos[2 * c + 1, 0] = float(sep)
+    nbr = torch.tensor([[i ^ 1] for i in range(2 * len(seps))], dtype=torch.int32)
     banner("md cutoff boundary")
     f = L.md(pos.to(DEV), nbr.to(DEV), t, 1.0, 1.0).cpu()
-    assert torch.all(f[:2] == 0)
-    assert torch.all(f[2:, 0] != 0)
+    assert torch.all(f[0:2] == 0)              # exactly t: r^2 = t^2 in binary32 too
+    assert torch.all(f[6:8, 0] != 0)           # 64 ulps inside
+    assert torch.all(f[8:10] == 0)             # 64 ulps outside
     check(f, pos, nbr, (t, 1.0, 1.0))
+
+
+def test_cutoff_pairs_where_binary32_rounding_decides(gpu_device):
+    # separations whose exact distance and binary32 r^2 fall on opposite
+    # sides of the cutoff: the kernel's result must equal the oracle's with
+    # that one term counted in or out
+    from tests.test_oracle_md import _near_cutoff_pairs
+
+    t = 2.5
+    qs = [q for v in _near_cutoff_pairs(t, count=6, seed=11).values() for q in v]
+    pos = torch.zeros((2 * len(qs), 4))
+    for c, q in enumerate(qs):
+        pos[2 * c, 0] = pos[2 * c + 1, 0] = 8.0 * c
+        pos[2 * c + 1, :3] += torch.from_numpy(q)
+    nbr = torch.tensor([[i ^ 1] for i in range(2 * len(qs))], dtype=torch.int32)
+    banner("md binary32 borderline pairs", len(qs))
+    check(L.md(pos.to(DEV), nbr.to(DEV), t, 1.0, 1.0), pos, nbr, (t, 1.0, 1.0))
 
 
 def test_bitwise_deterministic(gpu_device):
@@ -128,16 +212,11 @@ def test_paper_size_system_library_default_launch(gpu_device):
 
 
 @pytest.mark.parametrize("launch,shuffle", [("tuned", True), ("library default", True), ("library default", False)])
-def test_large_system_sampled(gpu_device, launch, shuffle):
-    import oracle
-
+def test_large_system(gpu_device, launch, shuffle):
     pos, nbr, params = W.md_system(W.MD_BOX_LARGE, shuffle=shuffle)
     banner("md 2^20 particles", launch, "random order" if shuffle else "lattice order")
     if launch == "tuned":
         f = L.md(pos.to(DEV), nbr.to(DEV), *params)
     else:
         f = _md_plain(pos, nbr, params)
-    f = f.cpu().numpy().astype(np.float64)
-    ref, mass = oracle.md(pos.numpy(), nbr.numpy(), *params, with_mass=True)
-    err = np.abs(f[:, :3] - ref)
-    assert np.all(err <= BAR * mass + 1e-30)
+    check(f, pos, nbr, params)

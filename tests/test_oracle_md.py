@@ -113,13 +113,43 @@ def test_cutoff_and_empty_slots():
     assert oracle.md(np.zeros((0, 4), np.float32), np.zeros((0, 3), np.int32), 1.0, 1.0, 1.0).shape == (0, 3)
 
 
-def test_cutoff_decision_is_binary32():
-    # a separation whose binary32 squared distance rounds onto t^2 is outside
-    # (strict <), whatever its binary64 square says
-    t = 1.25
+def _near_cutoff_pairs(t, count=4, seed=5):
+    """Separations q (p at the origin) within a few binary32 ulps of the
+    cutoff whose exact squared distance (rationals) is decided differently
+    by a binary32 evaluation ((dx dx + dy dy) + dz dz < binary32(t^2)): half
+    exactly inside, half exactly outside, each at least 1e-12 relative from
+    t^2, so a binary64 evaluation decides them correctly."""
+    from fractions import Fraction
+
+    rng = np.random.default_rng(seed)
+    t2, t2f = Fraction(t) ** 2, np.float32(t * t)
+    got = {True: [], False: []}
+    while min(len(v) for v in got.values()) < count:
+        d = rng.normal(size=3)
+        q = (d / np.linalg.norm(d) * t * (1 + int(rng.integers(-6, 7)) * 2.0 ** -24)).astype(np.float32)
+        sq = q * q
+        r2f = np.float32(np.float32(sq[0] + sq[1]) + sq[2])
+        exact = sum(Fraction(float(v)) ** 2 for v in q)
+        inside = exact < t2
+        if inside != bool(r2f < t2f) and abs(exact - t2) > Fraction(1, 10 ** 12) * t2 and len(got[inside]) < count:
+            got[inside].append(q)
+    return got
+
+
+def test_cutoff_is_the_exact_distance():
+    # updateF's test is distance < t: decided on the exact distance of the
+    # stored positions, also where a binary32 evaluation of r^2 decides the
+    # other way, and strictly (a pair at exactly t is outside)
+    t = 2.5
+    nbr = np.array([[1], [0]], np.int32)
+    for inside, qs in _near_cutoff_pairs(t).items():
+        for q in qs:
+            pos = np.zeros((2, 4), np.float32)
+            pos[1, :3] = q
+            f = oracle.md(pos, nbr, t, 1.0, 1.0)
+            assert bool(np.any(f != 0.0)) == inside, (q, inside)
     pos = np.zeros((2, 4), np.float32)
     pos[1, 0] = np.float32(t)
-    nbr = np.array([[1], [0]], np.int32)
     assert np.all(oracle.md(pos, nbr, t, 1.0, 1.0) == 0.0)
     pos[1, 0] = np.nextafter(np.float32(t), np.float32(0))
     assert np.all(oracle.md(pos, nbr, t, 1.0, 1.0)[:, 0] != 0.0)

@@ -49,8 +49,13 @@ MUTANTS = {
     "bs_cnd_wrong_scale": ("0.5 * erfc(-x / sqrt(2.0))", "0.5 * erfc(-x / 2.0)"),
     "md_force_sign_x": ("double dx = (double)p[0] - q[0]", "double dx = (double)q[0] - p[0]"),
     "md_drops_repulsion_factor": ("* s6 * 2.0 * s6;", "* s6 * s6;"),
-    "md_cutoff_not_squared": ("(float)(cutoff * cutoff)", "(float)(cutoff)"),
-    "md_ignores_cutoff": ("if (md_within(p, q, m->t2)) {", "if (1) {"),
+    "md_cutoff_compares_squared_distance": ("sqrt(d0 * d0 + d1 * d1 + d2 * d2) < t;", "d0 * d0 + d1 * d1 + d2 * d2 < t;"),
+    "md_cutoff_not_strict": ("sqrt(d0 * d0 + d1 * d1 + d2 * d2) < t;", "sqrt(d0 * d0 + d1 * d1 + d2 * d2) <= t;"),
+    "md_cutoff_rounded_like_binary32": (
+        "return sqrt(d0 * d0 + d1 * d1 + d2 * d2) < t;",
+        "volatile float fx = (float)d0, fy = (float)d1, fz = (float)d2, xx = fx * fx, yy = fy * fy, zz = fz * fz;"
+        " volatile float r2 = (xx + yy) + zz; return r2 < (float)(t * t);"),
+    "md_ignores_cutoff": ("if (md_within(p, q, m->t)) {", "if (1) {"),
     "md_sigma_not_squared": ("md_params m = {24.0 * epsilon, sigma * sigma,", "md_params m = {24.0 * epsilon, sigma,"),
 }
 
@@ -77,6 +82,7 @@ FAST_PINS = [
     md.test_zero_force_at_potential_minimum,
     md.test_newton_third_law_on_symmetric_lists,
     md.test_cutoff_and_empty_slots,
+    md.test_cutoff_is_the_exact_distance,
 ]
 
 
