@@ -52,7 +52,8 @@ sys.path.insert(0, ROOT)
 PEAK_GBS = 8000.0
 METRIC = "HBM GB/s and % of 8 TB/s peak: asum/dot/gemv FP32 vs BF16 and batched forms"
 COLD_BYTES = 1 << 30          # rotate buffer sets until at least this much is touched
-FORMS = ("small", "gemv", "half", "batch", "blackscholes", "md", "gemv16")
+ROOFLINE_LAUNCHES = 50        # the roofline kernel is timed on at least this many launches
+FORMS = ("large", "small", "gemv", "gemvrect", "half", "batch", "blackscholes", "md", "gemv16")
 
 
 def log(*a):
@@ -205,8 +206,12 @@ def main():
     # still drains, which reads ~1 us long); timing every step would add
     # ~5 us of idle GPU per step, so a sample is timed.
     sampled = [i for i in range(args.steps) if i % args.event_every == 0]
-    ev = L.HipEvents(2 * len(sampled))
-    ev_prev = L.HipEvents(2 * len(sampled))
+    # at least ROOFLINE_LAUNCHES timed launches: when the timed region holds
+    # fewer sampled steps, the same steps continue right after it (events on
+    # every one of them) until there are enough
+    extra = max(0, ROOFLINE_LAUNCHES - len(sampled))
+    ev = L.HipEvents(2 * (len(sampled) + extra))
+    ev_prev = L.HipEvents(2 * (len(sampled) + extra))
     slot_of = {i: j for j, i in enumerate(sampled)}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -216,19 +221,24 @@ def main():
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
-    durs = [ev.elapsed_ms(2 * j, 2 * j + 1) * 1e3 for j in range(len(sampled))]
+    for j in range(extra):
+        step(args.steps + j, dominant, ev, len(sampled) + j, ev_prev)
+    torch.cuda.synchronize()
+    durs = [ev.elapsed_ms(2 * j, 2 * j + 1) * 1e3 for j in range(len(sampled) + extra)]
     ev.close()
     ev_prev.close()
     dom_us = sum(durs) / len(durs)
     achieved = bytes_kernel[dominant] / (dom_us * 1e-6) / 1e9
     log("timed", args.steps, "steps", f"{ms_per_step:.4f} ms/step", f"{value:.1f} GB/s",
-        "dominant", dominant, f"{dom_us:.2f} us")
+        "dominant", dominant, f"{dom_us:.2f} us over {len(durs)} launches")
 
     roofline = {"bound": "hbm", "kernel": f"lift {dominant} (fp32, n=2^24)", "achieved": round(achieved, 1),
                 "peak": PEAK_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4),
                 "traffic": measured_traffic(dominant), "algorithmic_bytes": bytes_kernel[dominant],
                 "avg_us": round(dom_us, 3), "median_us": round(statistics.median(durs), 3),
-                "timed_launches": len(durs)}
+                "p10_us": round(sorted(durs)[len(durs) // 10], 3),
+                "p90_us": round(sorted(durs)[(9 * len(durs)) // 10], 3),
+                "timed_launches": len(durs), "in_timed_region": len(sampled)}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -242,22 +252,29 @@ def main():
         "kernels": kernels,
     }
 
-    # measured device-copy ceiling: torch's copy kernel, cold, 2 x 64 MiB per call
-    srcs = [s["xs"] for s in sets]
-    dsts = [s["out"] for s in sets]
-    us = _time_calls(lambda i: dsts[i].copy_(srcs[i]), nsets, stream, reps=100)
-    result["copy_ceiling"] = {"kernel": "torch copy_ (device to device)", "avg_us": round(us, 3),
-                              "GB_s": round(8 * n / (us * 1e-6) / 1e9, 1)}
-    log("copy ceiling", result["copy_ceiling"])
+    gpu_results = (float(sets[0]["ra"].item()), float(sets[0]["rd"].item()))
+    del sets, ptr
+    torch.cuda.empty_cache()
+    # measured ceiling: the library's flat read and copy kernels at the sizes
+    # of the step's kernels (and of the 2^27 form), best launch shape of a sweep
+    ceil = ceilings(L, dev, stream)
+    result["ceiling"] = ceil
+    # what each step kernel reaches of the ceiling of its own bytes
+    own = {"scal": "copy_2^24", "asum": "read_2^24", "dot": "read_2^25"}
+    for k in order:
+        c = ceil[own[k]]
+        kernels[k]["ceiling"] = own[k]
+        kernels[k]["frac_of_ceiling"] = round(c["avg_us"] / kernels[k]["avg_us"], 4)
+        kernels[k]["cold"]["frac_of_ceiling"] = round(c["cold_median_us"] / kernels[k]["cold"]["median_us"], 4)
+    roofline["ceiling_GB_s"] = ceil["read_2^25"]["GB_s"]
+    roofline["frac_of_ceiling"] = round(achieved / ceil["read_2^25"]["GB_s"], 4)
 
     # ------------------------------------------------------------ CPU oracle
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(x_cpu, y_cpu, alpha, args.cpu_seconds, sets[0], step_bytes)
+        result["cpu_baseline"] = cpu_baseline(x_cpu, y_cpu, alpha, args.cpu_seconds, gpu_results, step_bytes)
 
     # ------------------------------------------------------------ other forms
     if not args.no_forms:
-        del sets, ptr
-        torch.cuda.empty_cache()
         precision = {}
         result["forms"] = forms(L, W, dev, stream, tuple(args.forms.split(",")), precision)
         if not args.no_cpu_baseline and precision:
@@ -320,7 +337,9 @@ def cpu_baseline(x_cpu, y_cpu, alpha, seconds, gpu_set, step_bytes):
     asum, dot over the same host arrays): first the sequential composition on
     one thread, then its split-join form (rule 3d) on every host core this
     process may use, each for `seconds` (at least 5 steps); the median step
-    time gives the rate.  Timing includes the exact widening to binary64."""
+    time gives the rate.  Timing includes the exact widening to binary64.
+    gpu_set: the GPU's (asum, dot) results on the same data, for the error
+    report."""
     import oracle
 
     xs, ys = x_cpu.numpy(), y_cpu.numpy()
@@ -347,7 +366,7 @@ def cpu_baseline(x_cpu, y_cpu, alpha, seconds, gpu_set, step_bytes):
     tp, _ = timed(par)
     m1, mp = t1[len(t1) // 2], tp[len(tp) // 2]
     g1, gp = step_bytes / m1 / 1e9, step_bytes / mp / 1e9
-    ga, gd = float(gpu_set["ra"].item()), float(gpu_set["rd"].item())
+    ga, gd = gpu_set
     mass = oracle.dot_absmass(xs, ys)
     log("cpu oracle 1 thread:", len(t1), "steps, median", f"{m1 * 1e3:.1f} ms", f"{g1:.3f} GB/s;",
         threads, "threads:", len(tp), "steps, median", f"{mp * 1e3:.1f} ms", f"{gp:.3f} GB/s")
@@ -425,6 +444,64 @@ def _time_graph(fn, nsets, stream, reps=50, warm=5):
     return e0.elapsed_time(e1) * 1e3 / reps
 
 
+CEILING_SIZES = (("read", 24), ("read", 25), ("read", 27), ("read", 28), ("copy", 24), ("copy", 27))
+
+
+def ceilings(L, dev, stream, sizes=CEILING_SIZES):
+    """Achievable rate of one launch of a flat read / copy of 2^e floats: the
+    library's stream kernels over a sweep of launch shapes (work-group size,
+    loads in flight, work-groups per CU, chunked or interleaved steps), the
+    best back-to-back average on rotating buffers (cold Infinity Cache), and
+    the median of 200 single launches of that shape timed in their dispatch."""
+    import itertools
+
+    import torch
+
+    lib = L.library()
+    sh = stream.cuda_stream
+    out = {}
+    sink = torch.zeros(4, dtype=torch.float32, device=dev)
+    for kind, e in sizes:
+        n = 1 << e
+        moved = 4 * n * (2 if kind == "copy" else 1)
+        ns = max(2, -(-COLD_BYTES // moved))
+        xs = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(ns)]
+        outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(ns)] if kind == "copy" else None
+        best = None
+        for b, u, w, il in itertools.product((256, 512, 1024), (4, 8), (1, 2, 4, 8),
+                                             (L.LIFT_INTERLEAVE_CHUNK, L.LIFT_INTERLEAVE_STRIDE)):
+            kn = L.knobs(block=b, unroll=u, wg_per_cu=w, interleave=il)
+
+            def call(i, kn=kn):
+                if kind == "copy":
+                    st = lib.lift_stream_copy(n, xs[i].data_ptr(), outs[i].data_ptr(), ctypes_ref(kn), sh)
+                else:
+                    st = lib.lift_stream_read(n, xs[i].data_ptr(), sink.data_ptr(), ctypes_ref(kn), sh)
+                if st != 0:
+                    raise L.LiftError(st, f"lift_stream_{kind}")
+            us = _time_calls(call, ns, stream, reps=max(50, ns))
+            if best is None or us < best[0]:
+                best = (us, dict(block=b, unroll=u, wg_per_cu=w,
+                                 interleave="chunk" if il == L.LIFT_INTERLEAVE_CHUNK else "stride"), call)
+        us, knobs, call = best
+        d = _per_launch_us(L, lambda i, call=call: call(i % ns), 200)
+        med = d[len(d) // 2]
+        out[f"{kind}_2^{e}"] = {"bytes": moved, "avg_us": round(us, 3), "GB_s": round(moved / (us * 1e-6) / 1e9, 1),
+                                "frac_of_peak": round(moved / (us * 1e-6) / 1e9 / PEAK_GBS, 4),
+                                "cold_median_us": round(med, 3),
+                                "cold_median_GB_s": round(moved / (med * 1e-6) / 1e9, 1), "knobs": knobs}
+        log("ceiling", f"{kind}_2^{e}", out[f"{kind}_2^{e}"])
+        del xs, outs
+        torch.cuda.empty_cache()
+    return out
+
+
+def ctypes_ref(k):
+    import ctypes
+
+    return ctypes.byref(k)
+
+
 def forms(L, W, dev, stream, which=FORMS, precision=None):
     import torch
 
@@ -453,6 +530,51 @@ def forms(L, W, dev, stream, which=FORMS, precision=None):
                 st = lib.lift_gemv(size, size, alpha, As[i].data_ptr(), size, xd.data_ptr(), beta, yd.data_ptr(), sh)
                 assert st == 0
             rec(f"gemv_f32_{size}", _time_calls(call, ns, stream), nb, nb)
+            del As
+            torch.cuda.empty_cache()
+
+    if "large" in which:
+        # scal, asum and dot fp32 at n = 2^27 (512 MiB per vector: the paper's
+        # large vector size), plain entry points, two rotating buffer sets
+        n = W.LARGE_N
+        x, y, alpha = W.stream_vectors(n)
+        ns = 2
+        xs = [x.to(dev) for _ in range(ns)]
+        ys = [y.to(dev) for _ in range(ns)]
+        del x, y
+        res = torch.zeros((), dtype=torch.float32, device=dev)
+        outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(ns)]
+
+        def cs(i):
+            assert lib.lift_scal(n, alpha, xs[i].data_ptr(), outs[i].data_ptr(), sh) == 0
+
+        def ca(i):
+            assert lib.lift_asum(n, xs[i].data_ptr(), res.data_ptr(), wsp, wsb, sh) == 0
+
+        def cd(i):
+            assert lib.lift_dot(n, xs[i].data_ptr(), ys[i].data_ptr(), res.data_ptr(), wsp, wsb, sh) == 0
+        for name, fn, nb in (("scal", cs, 8 * n), ("asum", ca, 4 * n), ("dot", cd, 8 * n)):
+            rec(f"{name}_f32_2^27", _time_calls(fn, ns, stream, reps=40), nb, nb)
+            d = _per_launch_us(L, lambda i, fn=fn: fn(i % ns), 100)
+            out[f"{name}_f32_2^27"]["cold_median_us"] = round(d[len(d) // 2], 3)
+            out[f"{name}_f32_2^27"]["cold_median_GB_s"] = round(nb / (d[len(d) // 2] * 1e-6) / 1e9, 1)
+        del xs, ys, outs
+        torch.cuda.empty_cache()
+
+    if "gemvrect" in which:
+        # the paper's large gemv, 8192 x 16384, in both readings of its
+        # "vector size 8192": 8192 rows of 16384 columns (x of 16384) and
+        # 16384 rows of 8192 columns (x of 8192); A 512 MiB, two rotating copies
+        for m, k in ((8192, 16384), (16384, 8192)):
+            A, x, y, alpha, beta = W.gemv_rect(m, k)
+            nb = 4 * m * k + 4 * k + 8 * m
+            As = [A.to(dev) for _ in range(2)]
+            xd, yd = x.to(dev), y.to(dev)
+            del A
+
+            def cr(i, As=As, xd=xd, yd=yd, m=m, k=k, alpha=alpha, beta=beta):
+                assert lib.lift_gemv(m, k, alpha, As[i].data_ptr(), k, xd.data_ptr(), beta, yd.data_ptr(), sh) == 0
+            rec(f"gemv_f32_{m}x{k}", _time_calls(cr, 2, stream, reps=40), nb, nb)
             del As
             torch.cuda.empty_cache()
 
@@ -587,31 +709,24 @@ def out_pairs(pos, nbr, cutoff, dev):
 
 
 def batch_form(L, W, dev, stream, storage):
-    """The batch of 4096 reductions + 256 gemv: one batched run (two persistent launches) vs per-call kernels (eager and
-    captured in a graph) over the same problems.  Values are drawn on the GPU
-    (throughput only; parity is checked by the tests)."""
+    """The batch of 4096 reductions + 256 gemv: one batched run (two persistent
+    launches) vs per-call kernels (eager and captured in a graph) over the same
+    problems.  Values are drawn on the CPU with the workload's recipe (seed 5)
+    and copied to the device once."""
     import torch
 
     lib = L.library()
     spec = W.batch_shapes()
-    dt = {"f32": torch.float32, "bf16": torch.bfloat16}[storage]
-    g = torch.Generator(device=dev)
-    g.manual_seed(5)
+    reds, gemvs = W.batch_values(spec, storage)
     probs = []
-    for kind, n in zip(spec.red_kind, spec.red_len):
-        x = (torch.rand(n, generator=g, device=dev) * 2 - 1).to(dt)
-        probs.append(("dot", x, (torch.rand(n, generator=g, device=dev) * 2 - 1).to(dt)) if kind == "dot"
-                     else ("asum", x))
-    for m, n in spec.gemv_mn:
-        probs.append(("gemv", 1.0, torch.randn((m, n), generator=g, device=dev).to(dt),
-                      torch.randn(n, generator=g, device=dev), 0.5, torch.randn(m, generator=g, device=dev)))
-    tuned = None
-    try:
-        from paper_1502_02389_amd import tune
-        tuned = tune.lookup("batch", storage, "f32", 0)
-    except Exception:
-        tuned = None
-    b = L.Batch(probs, knobs=tuned)
+    for kind, x, y in reds:
+        probs.append(("dot", x.to(dev), y.to(dev)) if kind == "dot" else ("asum", x.to(dev)))
+    for A, x, y in gemvs:
+        probs.append(("gemv", W.GEMV_ALPHA, A.to(dev), x.to(dev), W.GEMV_BETA, y.to(dev)))
+    del reds, gemvs
+    # no knobs: the library's own choice (its autotuned entry for the batch on this device)
+    source, _ = L.lift_default_knobs("batch", {"f32": L.LIFT_F32, "bf16": L.LIFT_BF16}[storage], L.LIFT_ACC_F32, 0)
+    b = L.Batch(probs)
     fp32_bytes = sum(4 * n * (2 if k == "dot" else 1) + 4 for k, n in zip(spec.red_kind, spec.red_len)) + \
         sum(4 * m * n + 4 * n + 8 * m for m, n in spec.gemv_mn)
     ev = L.HipEvents(2)
@@ -689,7 +804,7 @@ def batch_form(L, W, dev, stream, storage):
            "per_call_eager_GB_s": round(bb / (eager_us * 1e-6) / 1e9, 1),
            "per_call_graph_us": round(graph_us, 1) if graph_us else None,
            "per_call_graph_GB_s": round(bb / (graph_us * 1e-6) / 1e9, 1) if graph_us else None,
-           "knobs": "tuned" if tuned is not None else "default"}
+           "knobs": {0: "default", 1: "tuned", 2: "forced"}[source]}
     log("form batch", storage, rec)
     b.close()
     return {f"batch_{storage}_4096red_256gemv": rec}

@@ -75,12 +75,17 @@ typedef enum lift_status {
     LIFT_EUNSUPPORTED = -4
 } lift_status;
 
-/* Storage / result types. */
+/* Storage / result types.  The two bound enumerators of lift_dtype and
+ * lift_acc are not values: they make every 32-bit integer a representable
+ * value of the type, so an out-of-range argument from any caller is read
+ * as such and rejected (LIFT_EINVAL) instead of being undefined in C++. */
 typedef enum lift_dtype {
     LIFT_F32 = 0,   /* IEEE binary32 */
     LIFT_BF16 = 1,  /* bfloat16: the upper 16 bits of a binary32 */
     LIFT_F16 = 2,   /* IEEE binary16 */
-    LIFT_F64 = 3    /* IEEE binary64 (reduction results only) */
+    LIFT_F64 = 3,   /* IEEE binary64 (reduction results only) */
+    LIFT_DTYPE_BOUND_LO_ = -0x7fffffff - 1,
+    LIFT_DTYPE_BOUND_HI_ = 0x7fffffff
 } lift_dtype;
 
 /* Accumulation variants for 16-bit and 32-bit storage. */
@@ -89,9 +94,11 @@ typedef enum lift_acc {
     LIFT_ACC_F32_COMP = 1,      /* compensated binary32: every partial sum is
                                    a (sum, error) pair propagated with the
                                    error-free TwoSum transformation */
-    LIFT_ACC_F32_F64COMBINE = 2 /* binary32 within a work-group, binary64 for
+    LIFT_ACC_F32_F64COMBINE = 2, /* binary32 within a work-group, binary64 for
                                    the final cross-work-group combine (gemv:
                                    for the cross-lane combine of each row) */
+    LIFT_ACC_BOUND_LO_ = -0x7fffffff - 1,
+    LIFT_ACC_BOUND_HI_ = 0x7fffffff
 } lift_acc;
 
 /* Values of lift_knobs.interleave: how the work-groups of asum and dot
@@ -110,7 +117,23 @@ typedef enum lift_interleave {
 /* Launch knobs: the parameters the paper's low-level expressions expose
  * (split factor, work-group size, vector width; Fig. 9 and Section 6.2)
  * plus the rows handled together by one wavefront in gemv.  A zero field
- * selects the library default for that field. */
+ * selects the library default for that field.
+ *
+ * Calls that take no knobs, or are passed knobs == NULL, run with
+ *   1. the environment override LIFT_FORCE_CONFIG="key=value,..." if set
+ *      (read once per process; keys block (or wg), vec, unroll, rpw, split,
+ *      wgcu, rowsplit, lanes, interleave = stride | chunk | 1 | 2; values
+ *      non-negative integers; an unknown key or malformed value makes every
+ *      such call return LIFT_EINVAL), applied as if the caller had passed
+ *      those knobs (fields the op does not use are ignored);
+ *   2. else the autotuned knobs for the call's op, storage, accumulation and
+ *      size bucket floor(log2(elements)) (gemv: m n; MD: n k; a batch: one
+ *      bucket) -- a table built into the library from the autotuner's
+ *      cache, used only on a device of the architecture and compute-unit
+ *      count it was tuned on;
+ *   3. else the library defaults.
+ * lift_default_knobs reports which applies.  Explicit knobs are never
+ * overridden. */
 typedef struct lift_knobs {
     int32_t block;         /* work-group size: 64, 128, 256, 512 or 1024
                               (batched form: at most 512; gemv lowers it to
@@ -334,6 +357,27 @@ void lift_batch_destroy(lift_batch *batch);
 
 /* ---- diagnostics ------------------------------------------------------ */
 
+/* Bandwidth reference kernels (measurement only; no operation of the paper).
+ * They move bytes the way the library's streaming kernels do -- 16-byte
+ * nontemporal loads, `unroll` in flight per lane, the reductions' partition
+ * into work-group chunks (split / wg_per_cu) or interleaved steps -- with no
+ * arithmetic and no cross-work-group combine, so a timed launch gives the
+ * achievable rate of one launch of that many bytes, the ceiling a reduction
+ * or a map of the same size is measured against.
+ * lift_stream_read reads x[0, n) and writes one word to *sink only if the
+ *   XOR fold of a lane's loads equals a fixed tag (sink: 4-byte aligned
+ *   device word owned by the caller; its contents are unspecified after the
+ *   call).
+ * lift_stream_copy writes out[i] = x[i] bit for bit (no overlap allowed).
+ * n must be a multiple of 4 and x (and out for the copy) 16-byte aligned;
+ * knobs: block, unroll, split, wg_per_cu, interleave (vec_bytes 0 or 16);
+ * NULL = 256 threads, 8 loads in flight, one work-group per compute unit.
+ * LIFT_EINVAL on a bad size, pointer, alignment or overlap. */
+lift_status lift_stream_read(int64_t n, const float *x, float *sink, const lift_knobs *knobs,
+                             hipStream_t stream);
+lift_status lift_stream_copy(int64_t n, const float *x, float *out, const lift_knobs *knobs,
+                             hipStream_t stream);
+
 /* Profiling hook.  The NEXT kernel launched by a lift_* call on the calling
  * thread is dispatched with `start` and `stop` recorded inside its own
  * dispatch packet (hipExtLaunchKernel), so hipEventElapsedTime(start, stop)
@@ -343,6 +387,18 @@ void lift_batch_destroy(lift_batch *batch);
  * it; a call rejected before launching leaves it armed; (NULL, NULL)
  * disarms it.  Exactly one NULL is LIFT_EINVAL. */
 lift_status lift_time_next_launch(hipEvent_t start, hipEvent_t stop);
+
+/* The knobs a call with knobs == NULL would run with on a device of
+ * architecture `arch` (e.g. "gfx950"; NULL = the current device, a HIP
+ * query) with `cus` compute units (ignored when arch is NULL): op is one of
+ * "scal", "asum", "dot", "gemv", "batch", "blackscholes", "md"; elements is
+ * the size the bucket is taken of (see lift_knobs).  Fills *out (all zero =
+ * the library defaults) and returns 2 if LIFT_FORCE_CONFIG applies, 1 for a
+ * tuned entry, 0 for the defaults; LIFT_EINVAL for an unknown op, storage
+ * or accumulation, a null pointer, negative elements or a malformed
+ * LIFT_FORCE_CONFIG; LIFT_EHIP if the current device cannot be queried. */
+int32_t lift_default_knobs(const char *op, lift_dtype storage, lift_acc acc, int64_t elements, const char *arch,
+                           int32_t cus, lift_knobs *out);
 
 /* Static description of a status code. */
 const char *lift_status_string(lift_status status);

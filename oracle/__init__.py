@@ -33,7 +33,10 @@ from . import patterns  # noqa: F401  (re-exported)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lift_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_DEFAULT = os.path.join(_HERE, "liboracle.so")
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+# ORACLE_LIB selects another build of the same source (the sanitizer build)
+_LIB = os.environ.get("ORACLE_LIB", _LIB_DEFAULT)
 
 F32, BF16, F16, F64 = 0, 1, 2, 3
 _CODES = {"f32": F32, "bf16": BF16, "f16": F16, "f64": F64}
@@ -43,18 +46,25 @@ _lock = threading.Lock()
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with gcc (no fast-math, no FP contraction)."""
-    if not force and os.path.exists(_LIB):
-        return _LIB
-    tmp = _LIB + ".tmp"
-    cmd = [
-        "gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fno-fast-math",
-        "-ffp-contract=off", "-pthread", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm",
-    ]
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile ``liboracle.so`` with gcc (no fast-math, no FP contraction);
+    with ``sanitize``, ``liboracle_san.so`` with clang's AddressSanitizer and
+    UndefinedBehaviorSanitizer (the runtime the library's sanitizer build
+    preloads; one process cannot hold gcc's and clang's)."""
+    lib = _LIB_SAN if sanitize else _LIB_DEFAULT
+    if not force and os.path.exists(lib):
+        return lib
+    tmp = lib + ".tmp"
+    if sanitize:
+        cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-std=c99", "-Wall", "-Wextra", "-fno-fast-math",
+               "-ffp-contract=off", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+               "-fno-omit-frame-pointer", "-pthread", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    else:
+        cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fno-fast-math",
+               "-ffp-contract=off", "-pthread", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def _configure(lib):
@@ -86,7 +96,7 @@ def _load():
     with _lock:
         if _lib is None:
             if not os.path.exists(_LIB):
-                build(force=True)
+                build(force=True, sanitize=_LIB == _LIB_SAN)
             _lib = _configure(ctypes.CDLL(_LIB))
     return _lib
 

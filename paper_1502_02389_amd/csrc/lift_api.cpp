@@ -11,8 +11,10 @@
 #include <cmath>
 #include <atomic>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <new>
 #include <numeric>
 #include <utility>
@@ -199,6 +201,168 @@ constexpr Knobs DEF_GEMV = {256, 16, 8, 1, 0, 0, 0, 1, 0};
 constexpr Knobs DEF_BATCH = {256, 16, 4, 1, 65536, 2, 1, 1, 0};
 constexpr Knobs DEF_BS = {256, 4, 4, 1, 0, 16, 1, 1, 0};
 constexpr Knobs DEF_MD = {256, 16, 2, 1, 0, 0, 1, 16, 0};
+constexpr Knobs DEF_STREAM = {256, 16, 8, 1, 0, 1, 1, 1, 0};
+
+// ---- knobs for calls that pass none --------------------------------------
+//
+// A call with knobs == NULL runs with, in this order: the LIFT_FORCE_CONFIG
+// override (read once from the environment), the autotuned entry for its
+// op / storage / accumulation / log2 size bucket on a device of the same
+// architecture and compute-unit count (generated at build time from the
+// tuner's cache), or the defaults above.
+
+enum TunedOp { TOP_SCAL = 0, TOP_ASUM, TOP_DOT, TOP_GEMV, TOP_BATCH, TOP_BS, TOP_MD, TOP_COUNT };
+
+struct TunedEntry {
+    const char *arch;  // e.g. "gfx950"; nullptr ends the table
+    int cus, op, storage, acc, bucket;
+    lift_knobs knobs;
+};
+
+const TunedEntry TUNED_TABLE[] = {
+#include "lift_tuned_table.inc"
+    {nullptr, 0, 0, 0, 0, 0, {0, 0, 0, 0, 0, 0, 0, 0, 0}},
+};
+
+const char *const TUNED_OP_NAMES[TOP_COUNT] = {"scal", "asum", "dot", "gemv", "batch", "blackscholes", "md"};
+
+int log2_bucket(int64_t elements)
+{
+    int b = 0;
+    while (elements > 1) {
+        elements >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+const TunedEntry *tuned_entry(const char *arch, int cus, int op, int storage, int acc, int64_t elements)
+{
+    const int bucket = op == TOP_BATCH ? 0 : log2_bucket(elements);
+    for (const TunedEntry *e = TUNED_TABLE; e->arch; ++e)
+        if (e->cus == cus && e->op == op && e->storage == storage && e->acc == acc && e->bucket == bucket &&
+            std::strcmp(e->arch, arch) == 0)
+            return e;
+    return nullptr;
+}
+
+// LIFT_FORCE_CONFIG="key=value,...": keys block (or wg), vec, unroll, rpw,
+// split, wgcu, rowsplit, lanes, interleave (stride | chunk); values are
+// non-negative integers.  Parsed once; a malformed string makes every call
+// without knobs fail with LIFT_EINVAL.
+struct Forced {
+    bool present = false, valid = true;
+    lift_knobs knobs{};
+};
+
+bool parse_forced(const char *text, lift_knobs *k)
+{
+    std::memset(k, 0, sizeof *k);
+    const char *p = text;
+    while (*p) {
+        const char *eq = std::strchr(p, '=');
+        if (!eq)
+            return false;
+        std::string key(p, eq);
+        const char *v = eq + 1;
+        const char *end = std::strchr(v, ',');
+        std::string val = end ? std::string(v, end) : std::string(v);
+        p = end ? end + 1 : v + val.size();
+        if (key == "interleave" && (val == "stride" || val == "chunk")) {
+            k->interleave = val == "stride" ? LIFT_INTERLEAVE_STRIDE : LIFT_INTERLEAVE_CHUNK;
+            continue;
+        }
+        if (val.empty() || val.size() > 12 || val.find_first_not_of("0123456789") != std::string::npos)
+            return false;
+        const long long x = std::stoll(val);
+        if (key == "block" || key == "wg")
+            k->block = (int32_t)x;
+        else if (key == "vec")
+            k->vec_bytes = (int32_t)x;
+        else if (key == "unroll")
+            k->unroll = (int32_t)x;
+        else if (key == "rpw")
+            k->rows_per_wave = (int32_t)x;
+        else if (key == "split")
+            k->split = (int64_t)x;
+        else if (key == "wgcu")
+            k->wg_per_cu = (int32_t)x;
+        else if (key == "rowsplit")
+            k->row_split = (int32_t)x;
+        else if (key == "lanes")
+            k->lanes_per_item = (int32_t)x;
+        else if (key == "interleave")
+            k->interleave = (int32_t)x;
+        else
+            return false;
+        if (x > INT32_MAX && key != "split")
+            return false;
+    }
+    return true;
+}
+
+const Forced &forced_config()
+{
+    static Forced f;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *env = std::getenv("LIFT_FORCE_CONFIG");
+        if (env && *env) {
+            f.present = true;
+            f.valid = parse_forced(env, &f.knobs);
+        }
+    });
+    return f;
+}
+
+// Architecture name (up to the first ':') and CU count of the current
+// device, cached per device; false if the device cannot be queried.
+bool device_identity(const char **arch, int *cus)
+{
+    static std::mutex mu;
+    static char names[MAX_DEVICES][64];
+    static int counts[MAX_DEVICES];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return false;
+    std::lock_guard<std::mutex> lock(mu);
+    if (counts[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return false;
+        size_t i = 0;
+        for (; i + 1 < sizeof names[dev] && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+            names[dev][i] = prop.gcnArchName[i];
+        names[dev][i] = 0;
+        counts[dev] = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : -1;
+    }
+    *arch = names[dev];
+    *cus = counts[dev];
+    return true;
+}
+
+// The knobs a call runs with: the caller's, else forced, else tuned for this
+// device, else nullptr (defaults).  *st is LIFT_EINVAL for a malformed
+// LIFT_FORCE_CONFIG.
+const lift_knobs *effective_knobs(const lift_knobs *given, int op, int storage, int acc, int64_t elements,
+                                  lift_status *st)
+{
+    *st = LIFT_OK;
+    if (given)
+        return given;
+    const Forced &f = forced_config();
+    if (f.present) {
+        if (!f.valid)
+            *st = LIFT_EINVAL;
+        return &f.knobs;
+    }
+    const char *arch = nullptr;
+    int cus = 0;
+    if (!device_identity(&arch, &cus))  // no device: defaults (the launch reports the HIP error)
+        return nullptr;
+    const TunedEntry *e = tuned_entry(arch, cus, op, storage, acc, elements);
+    return e ? &e->knobs : nullptr;
+}
 
 // Split a range of n elements of `ebytes` bytes at base address p into a
 // scalar head (up to the first vb-aligned address), whole vb-byte vectors,
@@ -301,13 +465,17 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
     if (overlaps(result, rb, x, xbytes) || overlaps(result, rb, y, op == OP_DOT ? xbytes : 0) ||
         overlaps(result, rb, ws, (int64_t)ws_bytes))
         return LIFT_EINVAL;
+    lift_status st = LIFT_OK;
+    knobs = effective_knobs(knobs, op == OP_DOT ? TOP_DOT : TOP_ASUM, xt, acc, n, &st);
+    if (st != LIFT_OK)
+        return st;
     Knobs k;
     Knobs def = DEF_REDUCE;
     if (op == OP_DOT) {
         def.unroll = 4;  // two streams: grid-stride steps of 4 loads of each in flight
         def.interleave = 1;
     }
-    lift_status st = resolve(knobs, def, eb, &k);
+    st = resolve(knobs, def, eb, &k);
     if (st != LIFT_OK)
         return st;
 
@@ -362,8 +530,12 @@ lift_status gemv_common(int64_t m, int64_t n, float alpha, int at, const void *A
     const int64_t abytes = m > 0 && n > 0 ? ((m - 1) * lda + n) * eb : 0;
     if (overlaps(y, m * 4, A, abytes) || overlaps(y, m * 4, x, m > 0 ? n * 4 : 0))
         return LIFT_EINVAL;
+    lift_status st = LIFT_OK;
+    knobs = effective_knobs(knobs, TOP_GEMV, at, acc, m * n, &st);
+    if (st != LIFT_OK)
+        return st;
     Knobs k;
-    lift_status st = resolve(knobs, DEF_GEMV, eb, &k);
+    st = resolve(knobs, DEF_GEMV, eb, &k);
     if (st != LIFT_OK)
         return st;
     if (m == 0)
@@ -479,6 +651,43 @@ bool any_overlap(std::vector<std::pair<uintptr_t, uintptr_t>> outs,
     return false;
 }
 
+// The bandwidth reference kernels: checks, then the reductions' partition
+// (chunk_for) over 16-byte vectors.
+lift_status stream_common(bool copy, int64_t n, const float *x, float *out, const lift_knobs *knobs,
+                          hipStream_t stream)
+{
+    if (n < 0 || n % 4 != 0)
+        return LIFT_EINVAL;
+    if (n > 0 && (!x || !out || !aligned(x, 16) || !aligned(out, copy ? 16 : 4)))
+        return LIFT_EINVAL;
+    if (overlaps(x, n * 4, out, copy ? n * 4 : 4))
+        return LIFT_EINVAL;
+    Knobs k;
+    lift_status st = resolve(knobs, DEF_STREAM, 4, &k);
+    if (st != LIFT_OK)
+        return st;
+    if (k.vec_bytes != 16)
+        return LIFT_EUNSUPPORTED;
+    if (n == 0)
+        return LIFT_OK;
+    const void *kern = stream_kernel(copy, k.unroll);
+    if (!kern)
+        return LIFT_EUNSUPPORTED;
+    int cus = 0;
+    st = cu_count(&cus);
+    if (st != LIFT_OK)
+        return st;
+    const int64_t nvec = n / 4;
+    const int64_t chunk = chunk_for(nvec, 4, k, cus, MAX_DISPATCH_ITEMS / k.block);
+    StreamArgs a;
+    a.x = x;
+    a.out = out;
+    a.nvec = nvec;
+    a.chunk = chunk;
+    a.interleave = k.interleave;
+    return launch(kern, std::max<int64_t>(1, (nvec + chunk - 1) / chunk), k.block, &a, stream);
+}
+
 }  // namespace
 
 // A planned batch: one launch over the reduction tiles ([0]) and one over
@@ -510,8 +719,12 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     if (rt != LIFT_F32 && rt != LIFT_F64)
         return LIFT_EINVAL;
     const int eb = elem_bytes(storage), rb = elem_bytes(rt);
+    lift_status st = LIFT_OK;
+    knobs = effective_knobs(knobs, TOP_BATCH, storage, acc, 0, &st);
+    if (st != LIFT_OK)
+        return st;
     Knobs k;
-    lift_status st = resolve(knobs, DEF_BATCH, eb, &k);
+    st = resolve(knobs, DEF_BATCH, eb, &k);
     if (st != LIFT_OK)
         return st;
     if (k.vec_bytes < 4)
@@ -740,8 +953,12 @@ lift_status lift_scal_ex(int64_t n, float alpha, const float *x, float *out, con
         return LIFT_EINVAL;
     if (x != out && overlaps(x, n * 4, out, n * 4))
         return LIFT_EINVAL;
+    lift_status st = LIFT_OK;
+    knobs = effective_knobs(knobs, TOP_SCAL, LIFT_F32, LIFT_ACC_F32, n, &st);
+    if (st != LIFT_OK)
+        return st;
     Knobs k;
-    lift_status st = resolve(knobs, DEF_SCAL, 4, &k);
+    st = resolve(knobs, DEF_SCAL, 4, &k);
     if (st != LIFT_OK)
         return st;
     if (k.vec_bytes < 4)
@@ -819,8 +1036,12 @@ lift_status lift_blackscholes_ex(int64_t n, const float *s, float strike, float 
     if (!(strike > 0.f) || !std::isfinite(strike) || !(volatility > 0.f) || !std::isfinite(volatility) ||
         !(years > 0.f) || !std::isfinite(years) || !std::isfinite(rate))
         return LIFT_EINVAL;
+    lift_status st = LIFT_OK;
+    knobs = effective_knobs(knobs, TOP_BS, LIFT_F32, LIFT_ACC_F32, n, &st);
+    if (st != LIFT_OK)
+        return st;
     Knobs k;
-    lift_status st = resolve(knobs, DEF_BS, 4, &k);
+    st = resolve(knobs, DEF_BS, 4, &k);
     if (st != LIFT_OK)
         return st;
     if (k.vec_bytes < 4)
@@ -885,8 +1106,12 @@ lift_status lift_md_ex(int64_t n, const float *pos, int64_t k, const int32_t *nb
     if (!(cutoff >= 0.f) || !std::isfinite(cutoff) || !(sigma > 0.f) || !std::isfinite(sigma) ||
         !std::isfinite(epsilon))
         return LIFT_EINVAL;
+    lift_status st = LIFT_OK;
+    knobs = effective_knobs(knobs, TOP_MD, LIFT_F32, LIFT_ACC_F32, n * k, &st);
+    if (st != LIFT_OK)
+        return st;
     Knobs kn;
-    lift_status st = resolve(knobs, DEF_MD, 4, &kn);
+    st = resolve(knobs, DEF_MD, 4, &kn);
     if (st != LIFT_OK)
         return st;
     if (kn.vec_bytes < 4 || kn.unroll > 4)
@@ -1038,6 +1263,50 @@ void lift_batch_destroy(lift_batch *b)
         if (ev)
             hipEventDestroy(ev);
     delete b;
+}
+
+lift_status lift_stream_read(int64_t n, const float *x, float *sink, const lift_knobs *knobs,
+                             hipStream_t stream)
+{
+    return stream_common(false, n, x, sink, knobs, stream);
+}
+
+lift_status lift_stream_copy(int64_t n, const float *x, float *out, const lift_knobs *knobs,
+                             hipStream_t stream)
+{
+    return stream_common(true, n, x, out, knobs, stream);
+}
+
+int32_t lift_default_knobs(const char *op, lift_dtype storage, lift_acc acc, int64_t elements, const char *arch,
+                           int32_t cus, lift_knobs *out)
+{
+    if (!op || !out || elements < 0)
+        return LIFT_EINVAL;
+    if (storage != LIFT_F32 && storage != LIFT_BF16 && storage != LIFT_F16)
+        return LIFT_EINVAL;
+    if (acc != LIFT_ACC_F32 && acc != LIFT_ACC_F32_COMP && acc != LIFT_ACC_F32_F64COMBINE)
+        return LIFT_EINVAL;
+    int top = -1;
+    for (int i = 0; i < TOP_COUNT; ++i)
+        if (std::strcmp(op, TUNED_OP_NAMES[i]) == 0)
+            top = i;
+    if (top < 0)
+        return LIFT_EINVAL;
+    std::memset(out, 0, sizeof *out);
+    const Forced &f = forced_config();
+    if (f.present) {
+        if (!f.valid)
+            return LIFT_EINVAL;
+        *out = f.knobs;
+        return 2;
+    }
+    if (!arch && !device_identity(&arch, &cus))
+        return LIFT_EHIP;
+    const TunedEntry *e = tuned_entry(arch, cus, top, storage, acc, elements);
+    if (!e)
+        return 0;
+    *out = e->knobs;
+    return 1;
 }
 
 const char *lift_status_string(lift_status s)

@@ -52,6 +52,18 @@ struct ScalArgs {
     float alpha;
 };
 
+// Bandwidth reference kernels: nvec 16-byte vectors of x read (and copied to
+// out), work-group b owning vectors [b * chunk, (b + 1) * chunk) or, with
+// interleave, steps b, b + G, ... of block * unroll vectors.  The read kernel
+// writes one word to out only if the XOR fold of its loads hits a fixed tag.
+struct StreamArgs {
+    const void *x;
+    void *out;
+    int64_t nvec;
+    int64_t chunk;
+    int32_t interleave;
+};
+
 // y = alpha * A x + beta * y; rows are handled R at a time by one wavefront;
 // each row has nvec aligned vectors followed by n - nvec * E scalar columns.
 struct GemvArgs {
@@ -132,6 +144,7 @@ const void *batch_kernel_f16(int acc, int vec_bytes, int unroll, bool gemv);
 // Kernel tables (nullptr where a combination is not built).
 const void *reduce_kernel(int dtype, int op, int acc, int vec_bytes, int unroll);
 const void *scal_kernel(int vec_bytes, int unroll);
+const void *stream_kernel(bool copy, int unroll);
 const void *gemv_kernel(int dtype, int acc, int vec_bytes, int rows, int unroll);
 
 // Per-dtype tables, one per translation unit.

@@ -18,7 +18,8 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblift.so")
+# LIFT_LIB selects another build of the library (the CPU sanitizer build)
+LIB_PATH = os.environ.get("LIFT_LIB", os.path.join(HERE, "liblift.so"))
 
 LIFT_OK, LIFT_EINVAL, LIFT_EWORKSPACE, LIFT_EHIP, LIFT_EUNSUPPORTED = 0, -1, -2, -3, -4
 LIFT_F32, LIFT_BF16, LIFT_F16, LIFT_F64 = 0, 1, 2, 3
@@ -111,6 +112,9 @@ SIGNATURES = {
     "lift_batch_info": (_i32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_int64)]),
     "lift_batch_destroy": (None, [_vp]),
+    "lift_stream_read": (_i32, [_i64, _vp, _vp, _kp, _vp]),
+    "lift_stream_copy": (_i32, [_i64, _vp, _vp, _kp, _vp]),
+    "lift_default_knobs": (_i32, [ctypes.c_char_p, _i32, _i32, _i64, ctypes.c_char_p, ctypes.c_int32, _kp]),
 }
 
 
@@ -198,6 +202,26 @@ def lift_md(n, pos, k, nbr, cutoff, epsilon, sigma, force, stream=0):
 
 def lift_md_ex(n, pos, k, nbr, cutoff, epsilon, sigma, force, knobs=None, stream=0):
     return _lib().lift_md_ex(n, pos, k, nbr, cutoff, epsilon, sigma, force, _kptr(knobs), stream)
+
+
+def lift_stream_read(n, x, sink, knobs=None, stream=0):
+    return _lib().lift_stream_read(n, x, sink, _kptr(knobs), stream)
+
+
+def lift_stream_copy(n, x, out, knobs=None, stream=0):
+    return _lib().lift_stream_copy(n, x, out, _kptr(knobs), stream)
+
+
+def lift_default_knobs(op, storage, acc, elements, arch=None, cus=0):
+    """(source, knobs dict) of a call without knobs: source 2 = LIFT_FORCE_CONFIG,
+    1 = the tuned table, 0 = the defaults (all-zero knobs); arch None = the
+    current device.  Raises LiftError on a negative status."""
+    k = lift_knobs()
+    st = _lib().lift_default_knobs(op.encode(), storage, acc, elements, arch.encode() if arch else None, cus,
+                                   ctypes.byref(k))
+    if st < 0:
+        raise LiftError(st, "lift_default_knobs")
+    return st, {f: getattr(k, f) for f, _ in lift_knobs._fields_}
 
 
 def lift_status_string(status):
@@ -331,20 +355,6 @@ def _check_tensor(t, name, dtypes):
         raise ValueError(f"{name} must be contiguous")
 
 
-_STORAGE = None
-
-
-def _tuned(op, dtype, acc, elements):
-    """Knobs from the autotuner's cache for this call shape (None = defaults)."""
-    global _STORAGE
-    torch = _torch()
-    if _STORAGE is None:
-        _STORAGE = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float16: "f16"}
-    from . import tune
-
-    return tune.lookup(op, _STORAGE[dtype], acc, elements)
-
-
 def _ok(status, what):
     if status != LIFT_OK:
         raise LiftError(status, what)
@@ -360,8 +370,6 @@ def scal(alpha, x, out=None, knobs=None):
     if out.numel() != x.numel():
         raise ValueError("out must match x")
     s = _stream_handle(x.device)
-    if knobs is None:
-        knobs = _tuned("scal", x.dtype, "f32", x.numel())
     _ok(lift_scal_ex(x.numel(), float(alpha), x.data_ptr(), out.data_ptr(), knobs, s), "lift_scal")
     return out
 
@@ -380,8 +388,6 @@ def _reduce(which, x, y, acc, result_dtype, knobs):
     s = _stream_handle(x.device)
     accc = ACC[acc] if isinstance(acc, str) else int(acc)
     rt = _dtype_code(result_dtype)
-    if knobs is None and isinstance(acc, str):
-        knobs = _tuned(which, x.dtype, acc, x.numel())
     if which == "asum":
         st = lift_asum_ex(x.numel(), _dtype_code(x.dtype), x.data_ptr(), accc, rt, result.data_ptr(),
                           ws.data_ptr(), ws.numel(), knobs, s)
@@ -416,8 +422,6 @@ def blackscholes(s, strike, rate, volatility, years, out=None, knobs=None):
     if out.numel() != 2 * n:
         raise ValueError("out must hold two floats per price")
     st = _stream_handle(s.device)
-    if knobs is None and n > 0:
-        knobs = _tuned("blackscholes", s.dtype, "f32", n)
     _ok(lift_blackscholes_ex(n, s.data_ptr(), float(strike), float(rate), float(volatility), float(years),
                              out.data_ptr(), knobs, st), "lift_blackscholes")
     return out
@@ -441,8 +445,6 @@ def md(pos, nbr, cutoff, epsilon, sigma, out=None, knobs=None):
     if out.numel() != 4 * n:
         raise ValueError("out must be (n, 4)")
     st = _stream_handle(pos.device)
-    if knobs is None and n > 0:
-        knobs = _tuned("md", pos.dtype, "f32", n * k)
     _ok(lift_md_ex(n, pos.data_ptr(), k, nbr.data_ptr(), float(cutoff), float(epsilon), float(sigma),
                    out.data_ptr(), knobs, st), "lift_md")
     return out
@@ -467,8 +469,6 @@ def gemv(alpha, A, x, beta, y, acc="f32", knobs=None, lda=None):
         raise ValueError("y must have one entry per row of A")
     s = _stream_handle(A.device)
     accc = ACC[acc] if isinstance(acc, str) else int(acc)
-    if knobs is None and isinstance(acc, str) and m * n > 0:
-        knobs = _tuned("gemv", A.dtype, acc, m * n)
     _ok(lift_gemv_ex(m, n, float(alpha), _dtype_code(A.dtype), A.data_ptr(), lda, x.data_ptr(),
                      float(beta), y.data_ptr(), accc, knobs, s), "lift_gemv")
     return y

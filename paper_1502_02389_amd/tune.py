@@ -11,11 +11,14 @@ Timing: back-to-back launches bracketed by one HIP event pair on the stream
 the kernels run on, operands rotated over enough copies (>= 1 GiB) that no
 launch finds them in the 256 MB Infinity Cache; best of `trials` repeats.
 
-Results persist in a JSON cache keyed by
-``op/storage/acc/bucket`` (bucket = floor(log2(elements))) plus the device
-name and CU count, so tuning resumes where it stopped and is reused by
-``lift.asum`` & co. when the caller passes no knobs.  ``LIFT_TUNE_CACHE``
-overrides the cache path.
+Results persist in a JSON cache of entries keyed by ``op/storage/acc/bucket``
+(bucket = floor(log2(elements))), recorded for one device: its architecture
+(e.g. gfx950) and compute-unit count.  ``lookup`` answers only for that
+device (None elsewhere), and the library build compiles the same entries
+into a table that C callers get when they pass no knobs on such a device
+(``lift_default_knobs`` reports it).  ``LIFT_TUNE_CACHE`` overrides the
+cache path read by ``lookup`` and written by ``--write``; the library's
+table is built from the package's ``tuning.json``.
 
 CLI:  python -m paper_1502_02389_amd.tune --ops asum,dot --sizes 24 [--write]
 """
@@ -69,9 +72,25 @@ def load_cache(path: str | None = None) -> dict:
     return _CACHE
 
 
-def lookup(op: str, storage: str, acc: str, elements: int):
-    """Tuned knobs for this call shape, or None (library defaults)."""
-    ent = load_cache()["entries"].get(key(op, storage, acc, elements))
+def current_device():
+    """(architecture, compute units) of cuda:0, e.g. ("gfx950", 256)."""
+    import torch
+
+    props = torch.cuda.get_device_properties(0)
+    return props.gcnArchName.split(":")[0], props.multi_processor_count
+
+
+def lookup(op: str, storage: str, acc: str, elements: int, device=None):
+    """Tuned knobs for this call shape on `device` ((arch, cus); None = the
+    current GPU), or None: no entry, or the cache was tuned on another
+    device (then the library's defaults apply)."""
+    data = load_cache()
+    meta = data.get("device") or {}
+    if device is None:
+        device = current_device()
+    if (meta.get("arch"), meta.get("cus")) != tuple(device):
+        return None
+    ent = data["entries"].get(key(op, storage, acc, elements))
     if not ent:
         return None
     return B.knobs(**ent["knobs"])
@@ -136,8 +155,9 @@ def grid(op: str, storage: str, quick: bool = False):
 
 
 class BatchOperands:
-    """The batched workload (reductions + gemv problems), drawn on the GPU;
-    each knob point plans its own batch over the same tensors."""
+    """The batched workload (reductions + gemv problems), drawn on the CPU with
+    the workload's recipe and copied to the device once; each knob point plans
+    its own batch over the same tensors."""
 
     def __init__(self, storage, seed=5):
         import torch
@@ -147,20 +167,12 @@ class BatchOperands:
         self.op, self.storage = "batch", storage
         dev = torch.device("cuda:0")
         spec = W.batch_shapes()
-        dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[storage]
-        g = torch.Generator(device=dev)
-        g.manual_seed(seed)
+        reds, gemvs = W.batch_values(spec, storage, seed=seed)
         self.problems = []
-        for kind, n in zip(spec.red_kind, spec.red_len):
-            x = (torch.rand(n, generator=g, device=dev) * 2 - 1).to(dt)
-            if kind == "dot":
-                self.problems.append(("dot", x, (torch.rand(n, generator=g, device=dev) * 2 - 1).to(dt)))
-            else:
-                self.problems.append(("asum", x))
-        for m, n in spec.gemv_mn:
-            self.problems.append(("gemv", 1.0, torch.randn((m, n), generator=g, device=dev).to(dt),
-                                  torch.randn(n, generator=g, device=dev), 0.5,
-                                  torch.randn(m, generator=g, device=dev)))
+        for kind, x, y in reds:
+            self.problems.append(("dot", x.to(dev), y.to(dev)) if kind == "dot" else ("asum", x.to(dev)))
+        for A, x, y in gemvs:
+            self.problems.append(("gemv", W.GEMV_ALPHA, A.to(dev), x.to(dev), W.GEMV_BETA, y.to(dev)))
         self.bytes = None
         self.sets = 1
 
@@ -338,7 +350,12 @@ def main(argv=None):
     import torch
 
     props = torch.cuda.get_device_properties(0)
-    meta = {"name": props.name, "cus": props.multi_processor_count, "lib": B.lift_version()}
+    arch, cus = current_device()
+    meta = {"name": props.name, "arch": arch, "cus": cus, "lib": B.lift_version()}
+    cached = load_cache().get("device")
+    if args.write and cached and cached.get("arch") and (cached.get("arch"), cached.get("cus")) != (arch, cus):
+        raise SystemExit(f"the cache holds entries tuned on {cached['arch']} / {cached['cus']} CUs; "
+                         f"this device is {arch} / {cus} CUs: set LIFT_TUNE_CACHE to a new file")
     entries = {}
 
     def log(msg):

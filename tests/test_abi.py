@@ -151,6 +151,17 @@ def wsb():
     (lambda: L.lift_md(8, X, 4, Y, 2.5, float("inf"), 1.0, R), L.LIFT_EINVAL),       # epsilon
     (lambda: L.lift_md(1 << 31, X, 4, Y, 2.5, 1.0, 1.0, R), L.LIFT_EINVAL),          # n too large
     (lambda: L.lift_md(0, X, 4, Y, 2.5, 1.0, 1.0, R), L.LIFT_OK),                    # empty: no-op
+    (lambda: L.lift_stream_read(-4, X, R), L.LIFT_EINVAL),
+    (lambda: L.lift_stream_read(6, X, R), L.LIFT_EINVAL),                            # not a multiple of 4
+    (lambda: L.lift_stream_read(8, X + 4, R), L.LIFT_EINVAL),                        # x not 16-aligned
+    (lambda: L.lift_stream_read(8, 0, R), L.LIFT_EINVAL),                            # null x
+    (lambda: L.lift_stream_read(8, X, 0), L.LIFT_EINVAL),                            # null sink
+    (lambda: L.lift_stream_read(8, X, X + 8), L.LIFT_EINVAL),                        # sink inside x
+    (lambda: L.lift_stream_read(8, X, R, B.knobs(vec_bytes=8)), L.LIFT_EUNSUPPORTED),
+    (lambda: L.lift_stream_read(8, X, R, B.knobs(unroll=3)), L.LIFT_EINVAL),
+    (lambda: L.lift_stream_copy(8, X, Y + 4), L.LIFT_EINVAL),                        # out not 16-aligned
+    (lambda: L.lift_stream_copy(8, X, X + 16), L.LIFT_EINVAL),                       # overlap
+    (lambda: L.lift_stream_copy(0, X, Y), L.LIFT_OK),                                # empty: no-op
 ])
 def test_rejects_before_any_hip_call(case, expect):
     assert case() == expect

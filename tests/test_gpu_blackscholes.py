@@ -1,11 +1,13 @@
 """GPU parity of BlackScholes (map(BSComputation) over stock prices).
 
-Bar: every call and put within 1e-5 of the binary64 oracle, measured against
+Bar: every call and put within 2e-6 of the binary64 oracle, measured against
 the magnitude of the two terms of the formula, s + K e^{-rT} (deep
 out-of-the-money prices are tiny differences of those terms, so a plain
 relative error is unbounded there).  The kernel is binary32 with the
 hardware log2 / exp2 / reciprocal and a fitted polynomial for the normal
-tail; the expected error is ~5e-7 of that scale.
+tail; the expected error is ~5e-7 of that scale (a few binary32 roundings
+of each term), so 2e-6 leaves a factor of 4 and still catches an error of
+8e-5 absolute at the workload's strike of 20.
 """
 import math
 
@@ -19,7 +21,7 @@ from tests.gpu_util import banner
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-BAR = 1e-5
+BAR = 2e-6
 
 
 def oracle_pairs(s, params):
@@ -40,17 +42,18 @@ def check(got, s, params):
     return worst
 
 
-@pytest.mark.parametrize("launch", ["tuned", "library default"])
+@pytest.mark.parametrize("launch", ["plain entry point", "library defaults"])
 def test_full_size_prices(gpu_device, launch):
     s, params = W.blackscholes_prices()
     banner("blackscholes 2^22", params, launch)
-    if launch == "tuned":
-        out = L.blackscholes(s.to(DEV), *params)
-    else:   # the plain entry point (the library's own launch): the call the benchmark times
-        sd = s.to(DEV)
-        out = torch.empty((s.numel(), 2), dtype=torch.float32, device=DEV)
+    sd = s.to(DEV)
+    out = torch.empty((s.numel(), 2), dtype=torch.float32, device=DEV)
+    if launch == "plain entry point":   # no knobs (the tuned entry on this device): the call the benchmark times
         assert L.lift_blackscholes(s.numel(), sd.data_ptr(), *params, out.data_ptr(),
                                    torch.cuda.current_stream().cuda_stream) == 0
+    else:                               # explicit all-zero knobs: the built-in defaults
+        assert L.lift_blackscholes_ex(s.numel(), sd.data_ptr(), *params, out.data_ptr(), L.knobs(),
+                                      torch.cuda.current_stream().cuda_stream) == 0
     check(out, s, params)
     # put-call parity holds on the GPU result too
     K, r, _, T = params

@@ -4,7 +4,9 @@ Bar (stated per test): integer-valued inputs whose partial sums stay below
 2^24 in magnitude are bit-exact under every knob set; binary32 results are
 within relative error 1e-5 of the oracle, measured as
   asum : |g - r| / r
-  dot  : |g - r| / sum |x_i y_i|             (r can be ~0 by cancellation)
+  dot  : |g - r| / sum |x_i y_i|             (r can be ~0 by cancellation);
+         for the seeded uniform workloads, whose |r| is far from 0, also
+         |g - r| / |r|
   gemv : |g_i - r_i| / (|alpha| sum_j |A_ij x_j| + |beta y_i|)   per row
 and scal is bit-exact: one correctly rounded binary32 multiply per element,
 which is the binary64 oracle's exact product rounded to binary32.
@@ -88,6 +90,10 @@ def test_dot_2p24(gpu_device):
     g = L.dot(x.to(DEV), y.to(DEV)).item()
     r, mass = o_dot(x, y)
     assert abs(g - r) <= TOL * mass, (g, r, mass)
+    # this input does not cancel (|r| ~ sqrt(n) / 3 >> 0): the plain relative
+    # bar holds as well
+    assert abs(r) > 1e-3 * mass ** 0.5
+    assert abs(g - r) <= TOL * abs(r), (g, r)
 
 
 def test_asum_2p24(gpu_device):

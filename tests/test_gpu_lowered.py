@@ -131,35 +131,46 @@ def _step_run():
     return _STEP
 
 
-def _default_split(n, cus):
-    # default launch: 256 lanes, 16-byte vectors, one chunk per compute unit
-    return -(-(n // 4) // cus) * 4
+def _plain_call_shape(op, n, cus):
+    """Launch shape of a plain asum / dot call (no knobs) on this device: the
+    knobs lift_default_knobs reports (the tuned entry, if any), with the
+    built-in default for every zero field -- 256 lanes, 16-byte vectors, 8
+    loads in flight (dot: 4), one work-group per compute unit, contiguous
+    chunks for asum and interleaved steps for dot."""
+    _, k = L.lift_default_knobs(op, L.LIFT_F32, 0, n)
+    block = k["block"] or 256
+    vb = k["vec_bytes"] or 16
+    unroll = k["unroll"] or (4 if op == "dot" else 8)
+    interleave = {0: op == "dot", 1: True, 2: False}[k["interleave"]]
+    e = vb // 4
+    split = k["split"] or -(-(n // e) // (cus * (k["wg_per_cu"] or 1))) * e
+    return LW.launch_shape(n, 4, vb, block, unroll, split, interleave=interleave)
 
 
 def test_step_asum_2p24_default_launch_matches_its_expression(gpu_device):
-    """asum of the bench step, default launch (contiguous chunks, 8 loads in
-    flight, ~1 work-group per compute unit): bit for bit."""
+    """asum of the bench step through the plain entry point (the library's
+    own launch on this device): bit for bit."""
     from tests import binary32 as F32B
 
     st = _step_run()
     n = len(st["xs"])
-    sa = LW.launch_shape(n, 4, 16, 256, 8, _default_split(n, st["cus"]))
-    assert sa.grid == st["cus"]
+    sa = _plain_call_shape("asum", n, st["cus"])
     pa = LW.evaluate(st["xs"], sa, add=F32B.add, absval=abs, zero=0.0)
-    assert np.float32(st["res"][0]).view(np.uint32) == np.float32(pa).view(np.uint32), (float(st["res"][0]), pa)
+    assert np.float32(st["res"][0]).view(np.uint32) == np.float32(pa).view(np.uint32), \
+        (float(st["res"][0]), pa, LW.render(sa))
 
 
 def test_step_dot_2p24_default_launch_matches_its_expression(gpu_device):
-    """dot of the bench step (the roofline kernel), default launch
-    (grid-stride steps of 4 loads per operand): bit for bit."""
+    """dot of the bench step (the roofline kernel) through the plain entry
+    point: bit for bit."""
     from tests import binary32 as F32B
 
     st = _step_run()
     n = len(st["xs"])
-    sd = LW.launch_shape(n, 4, 16, 256, 4, _default_split(n, st["cus"]), interleave=True)
-    assert sd.grid == st["cus"]
+    sd = _plain_call_shape("dot", n, st["cus"])
     pd = LW.evaluate_dot(st["xs"], st["ys"], sd, add=F32B.add, fma=F32B.fma, zero=0.0)
-    assert np.float32(st["res"][1]).view(np.uint32) == np.float32(pd).view(np.uint32), (float(st["res"][1]), pd)
+    assert np.float32(st["res"][1]).view(np.uint32) == np.float32(pd).view(np.uint32), \
+        (float(st["res"][1]), pd, LW.render(sd))
 
 
 # gemv: m, n, lda, storage, knobs (row_split, block, rows_per_wave, unroll, vec_bytes) -> the
@@ -211,21 +222,41 @@ def test_gemv_matches_lowered_rows_bitwise(gpu_device, case):
 
 @pytest.mark.parametrize("size,sample", [(4096, 128), (8192, 48), (16384, 16)])
 def test_gemv_default_launch_sampled_rows_bitwise(gpu_device, size, sample):
-    """gemv fp32 at the bench's sizes through the plain entry point (library
-    default launch: a work-group per row sized to it, x in registers, 8 loads
-    in flight), sampled rows against the row expression bit for bit."""
+    """gemv fp32 at the bench's sizes through the plain entry point (no
+    knobs: the library's tuned entry for the size on this device, else its
+    default -- a work-group per row sized to it, x in registers, 8 loads in
+    flight): the call equals, bit for bit, the same call with the reported
+    knobs passed explicitly, and sampled rows equal the row expression of
+    that launch bit for bit."""
     A, x, y, alpha, beta = W.gemv_square(size)
     banner("lowered gemv default", size)
     yd = y.to(DEV)
     Ad, xd = A.to(DEV), x.to(DEV)
-    assert L.lift_gemv(size, size, alpha, Ad.data_ptr(), size, xd.data_ptr(), beta, yd.data_ptr(),
-                       torch.cuda.current_stream().cuda_stream) == 0
+    s = torch.cuda.current_stream().cuda_stream
+    assert L.lift_gemv(size, size, alpha, Ad.data_ptr(), size, xd.data_ptr(), beta, yd.data_ptr(), s) == 0
     got = yd.cpu().numpy()
-    block = 64                                    # the documented choice: smallest work-group whose
-    while block * 8 < size // 4 and block < 512:  # one step of 8 loads covers the row
-        block *= 2
+    src, k = L.lift_default_knobs("gemv", L.LIFT_F32, 0, size * size)
+    if src:
+        ye = y.to(DEV)
+        assert L.lift_gemv_ex(size, size, alpha, L.LIFT_F32, Ad.data_ptr(), size, xd.data_ptr(), beta,
+                              ye.data_ptr(), 0, L.knobs(**k), s) == 0
+        assert np.array_equal(ye.cpu().numpy().view(np.uint32), got.view(np.uint32))
+    unroll = k["unroll"] or 8
+    vb = k["vec_bytes"] or 16
+    row_split = k["row_split"] or (2 if size // 4 <= 512 * unroll else 1)
+    if row_split == 1:
+        lanes = 64                                  # a wavefront per row group; each row's dot over 64 lanes
+    else:
+        if vb != 16:
+            vb = 4                                  # the work-group form reads 16 bytes or one element
+        lanes = k["block"]
+        if not lanes:                               # the documented choice: smallest work-group whose
+            lanes = 64                              # one step covers the row
+            while lanes * unroll < size // (vb // 4) and lanes < 512:
+                lanes *= 2
+        assert lanes <= 256, "a larger work-group may be lowered by the instance's launch bound"
     rows = sorted(np.random.default_rng(size).choice(size, sample, replace=False).tolist())
-    pred = _gemv_model_rows(A, x, y, alpha, beta, rows, block, 8, 16, 4)
+    pred = _gemv_model_rows(A, x, y, alpha, beta, rows, lanes, unroll, vb, 4)
     bad = [i for i, p in zip(rows, pred) if np.float32(got[i]).view(np.uint32) != np.float32(p).view(np.uint32)]
     assert not bad, bad[:5]
 

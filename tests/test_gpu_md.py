@@ -195,13 +195,19 @@ def test_bitwise_deterministic(gpu_device):
         assert torch.equal(L.md(pd, nd, *params), a)
 
 
-def _md_plain(pos, nbr, params):
-    """Forces through the plain entry point (the library's own launch): the
-    call the benchmark times."""
+def _md_plain(pos, nbr, params, defaults=False):
+    """Forces through the plain entry point (no knobs: the library's tuned
+    entry on this device), the call the benchmark times; or, with
+    ``defaults``, with explicit all-zero knobs (the built-in defaults)."""
     pd, nd = pos.to(DEV), nbr.to(DEV)
     out = torch.empty((pos.shape[0], 4), dtype=torch.float32, device=DEV)
-    assert L.lift_md(pos.shape[0], pd.data_ptr(), nbr.shape[1], nd.data_ptr(), *params, out.data_ptr(),
-                     torch.cuda.current_stream().cuda_stream) == 0
+    s = torch.cuda.current_stream().cuda_stream
+    if defaults:
+        assert L.lift_md_ex(pos.shape[0], pd.data_ptr(), nbr.shape[1], nd.data_ptr(), *params, out.data_ptr(),
+                            L.knobs(), s) == 0
+    else:
+        assert L.lift_md(pos.shape[0], pd.data_ptr(), nbr.shape[1], nd.data_ptr(), *params, out.data_ptr(),
+                         s) == 0
     return out
 
 
@@ -211,12 +217,10 @@ def test_paper_size_system_library_default_launch(gpu_device):
     check(_md_plain(pos, nbr, params), pos, nbr, params)
 
 
-@pytest.mark.parametrize("launch,shuffle", [("tuned", True), ("library default", True), ("library default", False)])
+@pytest.mark.parametrize("launch,shuffle", [("plain entry point", True), ("library defaults", True),
+                                            ("plain entry point", False)])
 def test_large_system(gpu_device, launch, shuffle):
     pos, nbr, params = W.md_system(W.MD_BOX_LARGE, shuffle=shuffle)
     banner("md 2^20 particles", launch, "random order" if shuffle else "lattice order")
-    if launch == "tuned":
-        f = L.md(pos.to(DEV), nbr.to(DEV), *params)
-    else:
-        f = _md_plain(pos, nbr, params)
+    f = _md_plain(pos, nbr, params, defaults=launch == "library defaults")
     check(f, pos, nbr, params)

@@ -119,19 +119,19 @@ def test_f64combine_result_carries_more_digits(gpu_device):
     assert e64 <= max(e32, 1e-7)
 
 
-@pytest.mark.parametrize("launch", ["tuned", "library default"])
+@pytest.mark.parametrize("launch", ["plain entry point", "library defaults"])
 @pytest.mark.parametrize("acc", ACCS)
 def test_half_gemv_bf16(gpu_device, acc, launch):
     A, x, y, alpha, beta = _gemv_operands()
     banner("bf16 gemv 16384", acc, launch)
     yd = y.to(DEV)
-    if launch == "tuned":
-        L.gemv(alpha, _gemv_dev(A), x.to(DEV), beta, yd, acc=acc)
-    else:   # the raw entry point with no knobs: the call the benchmark times
-        size = A.shape[0]
-        xd = x.to(DEV)
-        assert L.lift_gemv_ex(size, size, alpha, L.LIFT_BF16, _gemv_dev(A).data_ptr(), size, xd.data_ptr(), beta,
-                              yd.data_ptr(), ACC_CODE[acc], None, torch.cuda.current_stream().cuda_stream) == 0
+    size = A.shape[0]
+    xd = x.to(DEV)
+    # no knobs (the tuned entry on this device): the call the benchmark
+    # times; or explicit all-zero knobs: the built-in defaults
+    kn = None if launch == "plain entry point" else L.knobs()
+    assert L.lift_gemv_ex(size, size, alpha, L.LIFT_BF16, _gemv_dev(A).data_ptr(), size, xd.data_ptr(), beta,
+                          yd.data_ptr(), ACC_CODE[acc], kn, torch.cuda.current_stream().cuda_stream) == 0
     r, mass = _gemv_ref()
     g = yd.cpu().numpy().astype(np.float64)
     err = np.abs(g - r) / mass

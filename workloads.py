@@ -52,6 +52,7 @@ def integers(shape, lo: int, hi: int, g: torch.Generator, storage: str = "f32") 
 
 ASUM_SMALL_N = 1 << 20      # asum, single vector
 STREAM_N = 1 << 24          # scal/asum/dot, 64 MiB per fp32 vector
+LARGE_N = 1 << 27           # scal/asum/dot, 512 MiB per fp32 vector (the paper's 128M size)
 STREAM_ALPHA = 2.5
 GEMV_SIZES = (4096, 8192)   # square gemv
 GEMV_ALPHA, GEMV_BETA = 1.0, 0.5
@@ -88,6 +89,16 @@ def gemv_square(size: int):
     A = normal((size, size), g)
     x = normal(size, g)
     y = normal(size, g)
+    return A, x, y, GEMV_ALPHA, GEMV_BETA
+
+
+def gemv_rect(m: int, n: int):
+    """gemv operands A (m x n), x (n), y (m) ~ normal(0, 1), seed 2, drawn in
+    the order A, x, y; alpha 1, beta 0.5."""
+    g = gen(2)
+    A = normal((m, n), g)
+    x = normal(n, g)
+    y = normal(m, g)
     return A, x, y, GEMV_ALPHA, GEMV_BETA
 
 
