@@ -100,6 +100,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--event-every", type=int, default=20,
                     help="time the dominant kernel in every k-th step of the timed region")
+    ap.add_argument("--stamps", default=None, metavar="OPS",
+                    help="diagnostic only: per-work-group clock stamps of the step's asum / dot launches "
+                         "(e.g. asum,dot); prints a JSON summary and exits")
+    ap.add_argument("--stamp-n", type=int, default=24, help="log2 n for --stamps")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -120,6 +124,10 @@ def main():
     sh = stream.cuda_stream
     props = torch.cuda.get_device_properties(dev)
     log("device", props.name, "CUs", props.multi_processor_count, "lib", L.lift_version())
+
+    if args.stamps:
+        print(json.dumps(stamp_report(L, W, dev, stream, args.stamps.split(","), 1 << args.stamp_n)), flush=True)
+        return
 
     # ------------------------------------------------------------ main step
     n = W.STREAM_N
@@ -281,6 +289,81 @@ def main():
             result["cpu_baseline"]["precision_forms_vs_oracle"] = precision_errors(precision)
 
     print(json.dumps(result), flush=True)
+
+
+def stamp_report(L, W, dev, stream, ops, n, launches=40):
+    """Where the time of a plain asum / dot launch goes, from per-work-group
+    wall-clock stamps (lift_stamp_next_launch) of `launches` launches on
+    rotating buffer sets (cold Infinity Cache), each also timed by HIP events
+    in its dispatch.  Per launch, relative to the first work-group's entry:
+    entry spread (dispatch ramp), first and last end of a streaming loop,
+    stream time per work-group, work-group tree, partial store, arrival, and
+    the combine tail from the last streaming loop's end to the result; the
+    medians over launches are reported."""
+    import torch
+
+    lib = L.library()
+    sh = stream.cuda_stream
+    x_cpu, y_cpu, _ = W.stream_vectors(n)
+    per_set = 8 * n
+    ns = max(2, -(-COLD_BYTES // per_set))
+    xs = [x_cpu.to(dev) for _ in range(ns)]
+    ys = [y_cpu.to(dev) for _ in range(ns)]
+    ws = L.workspace(dev)
+    res = torch.zeros((), device=dev)
+    cap = L.lift_max_workgroups()
+    buf = torch.zeros((cap, 8), dtype=torch.int64, device=dev)
+    out = {"n": n, "launches": launches}
+    for op in ops:
+        def call(i, op=op):
+            if op == "asum":
+                st = lib.lift_asum(n, xs[i].data_ptr(), res.data_ptr(), ws.data_ptr(), ws.numel(), sh)
+            else:
+                st = lib.lift_dot(n, xs[i].data_ptr(), ys[i].data_ptr(), res.data_ptr(), ws.data_ptr(), ws.numel(), sh)
+            if st != 0:
+                raise L.LiftError(st, f"lift_{op}")
+        for i in range(5):
+            call(i % ns)
+        rows = []
+        ev = L.HipEvents(2)
+        for i in range(launches):
+            buf.zero_()
+            torch.cuda.synchronize()
+            st, khz = L.lift_stamp_next_launch(buf.data_ptr(), cap)
+            assert st == 0 and khz > 0
+            assert L.lift_time_next_launch(ev.events[0], ev.events[1]) == 0
+            call(i % ns)
+            torch.cuda.synchronize()
+            ev_us = ev.elapsed_ms(0, 1) * 1e3
+            b = buf.cpu().numpy()
+            g = int((b[:, 0] != 0).sum())
+            b = b[:g].astype("float64")
+            us = 1e3 / khz                         # microseconds per tick
+            t0 = b[:, 0].min()
+            last = int(((b[:, 6].astype("int64") >> 32) & 1).argmax())
+            rows.append({
+                "event_us": ev_us,
+                "span_us": (b[:, 5].max() - t0) * us,
+                "entry_spread_us": (b[:, 0].max() - t0) * us,
+                "first_stream_end_us": (b[:, 1].min() - t0) * us,
+                "last_stream_end_us": (b[:, 1].max() - t0) * us,
+                "stream_median_us": float(statistics.median((b[:, 1] - b[:, 0]) * us)),
+                "tree_median_us": float(statistics.median((b[:, 2] - b[:, 1]) * us)),
+                "store_median_us": float(statistics.median((b[:, 3] - b[:, 2]) * us)),
+                "arrive_median_us": float(statistics.median((b[:, 4] - b[:, 3]) * us)),
+                "last_tree_done_us": (b[:, 2].max() - t0) * us,
+                "last_arrival_us": (b[:, 4].max() - t0) * us,
+                "tail_after_last_stream_us": (b[last, 5] - b[:, 1].max()) * us,
+                "combine_us": (b[last, 5] - b[last, 4]) * us,
+                "grid": g,
+                "xccs": len(set(((b[:, 6].astype("int64") >> 16) & 0xF).tolist())),
+            })
+        ev.close()
+        summary = {k: round(statistics.median(r[k] for r in rows), 3) for k in rows[0]}
+        summary["knobs"] = L.lift_default_knobs(op, L.LIFT_F32, 0, n)[1]
+        out[op] = summary
+        log("stamps", op, summary)
+    return out
 
 
 def precision_errors(precision):

@@ -127,8 +127,8 @@ typedef enum lift_interleave {
  *      such call return LIFT_EINVAL), applied as if the caller had passed
  *      those knobs (fields the op does not use are ignored);
  *   2. else the autotuned knobs for the call's op, storage, accumulation and
- *      size bucket floor(log2(elements)) (gemv: m n; MD: n k; a batch: one
- *      bucket) -- a table built into the library from the autotuner's
+ *      size bucket floor(log2(elements)) (gemv: m n, and floor(log2(n)) of
+ *      its rows; MD: n k; a batch: one bucket) -- a table built into the library from the autotuner's
  *      cache, used only on a device of the architecture and compute-unit
  *      count it was tuned on;
  *   3. else the library defaults.
@@ -388,17 +388,35 @@ lift_status lift_stream_copy(int64_t n, const float *x, float *out, const lift_k
  * disarms it.  Exactly one NULL is LIFT_EINVAL. */
 lift_status lift_time_next_launch(hipEvent_t start, hipEvent_t stop);
 
+/* Diagnostic hook: the NEXT asum or dot launch on the calling thread (binary32
+ * storage and accumulation, 16-byte loads) runs the stamped instance of its
+ * kernel, identical in arithmetic, which writes 8 words per work-group into
+ * `stamps` (device memory owned by the caller, `capacity` work-groups):
+ * readings of the device's constant wall clock at entry, when its streaming
+ * loop is done, after its work-group tree, once its partial is stored, once
+ * its arrival is counted, and at its end (the combining work-group: after
+ * the combine), then ids (bit 32: the work-group that combined; bits 16-19:
+ * its XCC; bits 0-7: HW_ID[15:8], CU / shader array / shader engine), then
+ * one unused word.  *clock_khz receives the clock's rate.  One-shot; that
+ * launch fails with LIFT_EUNSUPPORTED for another storage, accumulation or
+ * vector width and LIFT_EINVAL if its grid exceeds `capacity` (the hook is
+ * cleared either way).  stamps == NULL disarms it.  LIFT_EINVAL: capacity
+ * <= 0, stamps not 8-byte aligned or clock_khz NULL. */
+lift_status lift_stamp_next_launch(uint64_t *stamps, int64_t capacity, int32_t *clock_khz);
+
 /* The knobs a call with knobs == NULL would run with on a device of
  * architecture `arch` (e.g. "gfx950"; NULL = the current device, a HIP
  * query) with `cus` compute units (ignored when arch is NULL): op is one of
  * "scal", "asum", "dot", "gemv", "batch", "blackscholes", "md"; elements is
- * the size the bucket is taken of (see lift_knobs).  Fills *out (all zero =
- * the library defaults) and returns 2 if LIFT_FORCE_CONFIG applies, 1 for a
- * tuned entry, 0 for the defaults; LIFT_EINVAL for an unknown op, storage
- * or accumulation, a null pointer, negative elements or a malformed
- * LIFT_FORCE_CONFIG; LIFT_EHIP if the current device cannot be queried. */
-int32_t lift_default_knobs(const char *op, lift_dtype storage, lift_acc acc, int64_t elements, const char *arch,
-                           int32_t cus, lift_knobs *out);
+ * the size the bucket is taken of (see lift_knobs); row_length is gemv's n
+ * (its entries are also keyed by floor(log2(n)); ignored for other ops).
+ * Fills *out (all zero = the library defaults) and returns 2 if
+ * LIFT_FORCE_CONFIG applies, 1 for a tuned entry, 0 for the defaults;
+ * LIFT_EINVAL for an unknown op, storage or accumulation, a null pointer,
+ * negative sizes or a malformed LIFT_FORCE_CONFIG; LIFT_EHIP if the current
+ * device cannot be queried. */
+int32_t lift_default_knobs(const char *op, lift_dtype storage, lift_acc acc, int64_t elements, int64_t row_length,
+                           const char *arch, int32_t cus, lift_knobs *out);
 
 /* Static description of a status code. */
 const char *lift_status_string(lift_status status);

@@ -16,4 +16,5 @@ from .lift import (  # noqa: F401
     lift_batch_capture, lift_batch_info, lift_batch_destroy, LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV,
     blackscholes, lift_blackscholes, lift_blackscholes_ex, md, lift_md, lift_md_ex,
     lift_stream_read, lift_stream_copy, lift_default_knobs,
+    lift_stamp_next_launch,
 )

@@ -31,6 +31,8 @@ namespace {
 thread_local int g_last_hip_error = 0;
 thread_local hipEvent_t g_time_start = nullptr;  // armed by lift_time_next_launch
 thread_local hipEvent_t g_time_stop = nullptr;
+thread_local uint64_t *g_stamps = nullptr;       // armed by lift_stamp_next_launch
+thread_local int64_t g_stamp_capacity = 0;
 
 constexpr int MAX_DEVICES = 64;
 std::atomic<int> g_cu_count[MAX_DEVICES];
@@ -216,12 +218,13 @@ enum TunedOp { TOP_SCAL = 0, TOP_ASUM, TOP_DOT, TOP_GEMV, TOP_BATCH, TOP_BS, TOP
 struct TunedEntry {
     const char *arch;  // e.g. "gfx950"; nullptr ends the table
     int cus, op, storage, acc, bucket;
+    int row_bucket;    // gemv: floor(log2(n)); -1: any
     lift_knobs knobs;
 };
 
 const TunedEntry TUNED_TABLE[] = {
 #include "lift_tuned_table.inc"
-    {nullptr, 0, 0, 0, 0, 0, {0, 0, 0, 0, 0, 0, 0, 0, 0}},
+    {nullptr, 0, 0, 0, 0, 0, -1, {0, 0, 0, 0, 0, 0, 0, 0, 0}},
 };
 
 const char *const TUNED_OP_NAMES[TOP_COUNT] = {"scal", "asum", "dot", "gemv", "batch", "blackscholes", "md"};
@@ -236,12 +239,14 @@ int log2_bucket(int64_t elements)
     return b;
 }
 
-const TunedEntry *tuned_entry(const char *arch, int cus, int op, int storage, int acc, int64_t elements)
+const TunedEntry *tuned_entry(const char *arch, int cus, int op, int storage, int acc, int64_t elements,
+                              int64_t row_length)
 {
     const int bucket = op == TOP_BATCH ? 0 : log2_bucket(elements);
+    const int row_bucket = log2_bucket(row_length);
     for (const TunedEntry *e = TUNED_TABLE; e->arch; ++e)
         if (e->cus == cus && e->op == op && e->storage == storage && e->acc == acc && e->bucket == bucket &&
-            std::strcmp(e->arch, arch) == 0)
+            (e->row_bucket < 0 || e->row_bucket == row_bucket) && std::strcmp(e->arch, arch) == 0)
             return e;
     return nullptr;
 }
@@ -345,7 +350,7 @@ bool device_identity(const char **arch, int *cus)
 // device, else nullptr (defaults).  *st is LIFT_EINVAL for a malformed
 // LIFT_FORCE_CONFIG.
 const lift_knobs *effective_knobs(const lift_knobs *given, int op, int storage, int acc, int64_t elements,
-                                  lift_status *st)
+                                  lift_status *st, int64_t row_length = 0)
 {
     *st = LIFT_OK;
     if (given)
@@ -360,7 +365,7 @@ const lift_knobs *effective_knobs(const lift_knobs *given, int op, int storage, 
     int cus = 0;
     if (!device_identity(&arch, &cus))  // no device: defaults (the launch reports the HIP error)
         return nullptr;
-    const TunedEntry *e = tuned_entry(arch, cus, op, storage, acc, elements);
+    const TunedEntry *e = tuned_entry(arch, cus, op, storage, acc, elements, row_length);
     return e ? &e->knobs : nullptr;
 }
 
@@ -438,9 +443,9 @@ const void *gemv_split_table(int dt, int acc, int vb, int rows, int unroll, bool
     }
 }
 
-lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *y, int acc, int rt,
-                          void *result, void *ws, size_t ws_bytes, const lift_knobs *knobs,
-                          hipStream_t stream)
+// Checks of a reduction's operands (everything but the workspace).
+lift_status reduce_check(int op, int64_t n, int xt, const void *x, const void *y, int acc, int rt,
+                         const void *result)
 {
     if (n < 0)
         return LIFT_EINVAL;
@@ -457,13 +462,25 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
         return LIFT_EINVAL;
     if (op == OP_DOT && n > 0 && (!y || !aligned(y, eb)))
         return LIFT_EINVAL;
+    const int64_t xbytes = n * eb;
+    if (overlaps(result, rb, x, xbytes) || overlaps(result, rb, y, op == OP_DOT ? xbytes : 0))
+        return LIFT_EINVAL;
+    return LIFT_OK;
+}
+
+lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *y, int acc, int rt,
+                          void *result, void *ws, size_t ws_bytes, const lift_knobs *knobs,
+                          hipStream_t stream)
+{
+    lift_status st0 = reduce_check(op, n, xt, x, y, acc, rt, result);
+    if (st0 != LIFT_OK)
+        return st0;
+    const int eb = elem_bytes(xt), rb = elem_bytes(rt);
     if (!ws || ws_bytes < lift_workspace_bytes())
         return LIFT_EWORKSPACE;
     if (!aligned(ws, 16))
         return LIFT_EINVAL;
-    const int64_t xbytes = n * eb;
-    if (overlaps(result, rb, x, xbytes) || overlaps(result, rb, y, op == OP_DOT ? xbytes : 0) ||
-        overlaps(result, rb, ws, (int64_t)ws_bytes))
+    if (overlaps(result, rb, ws, (int64_t)ws_bytes))
         return LIFT_EINVAL;
     lift_status st = LIFT_OK;
     knobs = effective_knobs(knobs, op == OP_DOT ? TOP_DOT : TOP_ASUM, xt, acc, n, &st);
@@ -509,6 +526,20 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
     a.result = result;
     a.result_f64 = rt == LIFT_F64;
     a.interleave = k.interleave;
+    a.stamps = nullptr;
+    if (g_stamps) {  // the stamped instance of the same kernel (one-shot)
+        uint64_t *buf = g_stamps;
+        const int64_t cap = g_stamp_capacity;
+        g_stamps = nullptr;
+        if (xt != LIFT_F32 || acc != LIFT_ACC_F32 || vb != 16)
+            return LIFT_EUNSUPPORTED;
+        if (grid > cap)
+            return LIFT_EINVAL;
+        kern = reduce_kernel_stamped_f32(op, k.unroll);
+        if (!kern)
+            return LIFT_EUNSUPPORTED;
+        a.stamps = buf;
+    }
     return launch(kern, grid, k.block, &a, stream);
 }
 
@@ -531,7 +562,7 @@ lift_status gemv_common(int64_t m, int64_t n, float alpha, int at, const void *A
     if (overlaps(y, m * 4, A, abytes) || overlaps(y, m * 4, x, m > 0 ? n * 4 : 0))
         return LIFT_EINVAL;
     lift_status st = LIFT_OK;
-    knobs = effective_knobs(knobs, TOP_GEMV, at, acc, m * n, &st);
+    knobs = effective_knobs(knobs, TOP_GEMV, at, acc, m * n, &st, n);
     if (st != LIFT_OK)
         return st;
     Knobs k;
@@ -1277,10 +1308,10 @@ lift_status lift_stream_copy(int64_t n, const float *x, float *out, const lift_k
     return stream_common(true, n, x, out, knobs, stream);
 }
 
-int32_t lift_default_knobs(const char *op, lift_dtype storage, lift_acc acc, int64_t elements, const char *arch,
-                           int32_t cus, lift_knobs *out)
+int32_t lift_default_knobs(const char *op, lift_dtype storage, lift_acc acc, int64_t elements, int64_t row_length,
+                           const char *arch, int32_t cus, lift_knobs *out)
 {
-    if (!op || !out || elements < 0)
+    if (!op || !out || elements < 0 || row_length < 0)
         return LIFT_EINVAL;
     if (storage != LIFT_F32 && storage != LIFT_BF16 && storage != LIFT_F16)
         return LIFT_EINVAL;
@@ -1302,7 +1333,7 @@ int32_t lift_default_knobs(const char *op, lift_dtype storage, lift_acc acc, int
     }
     if (!arch && !device_identity(&arch, &cus))
         return LIFT_EHIP;
-    const TunedEntry *e = tuned_entry(arch, cus, top, storage, acc, elements);
+    const TunedEntry *e = tuned_entry(arch, cus, top, storage, acc, elements, row_length);
     if (!e)
         return 0;
     *out = e->knobs;
@@ -1329,6 +1360,27 @@ lift_status lift_time_next_launch(hipEvent_t start, hipEvent_t stop)
         return LIFT_EINVAL;
     g_time_start = start;
     g_time_stop = stop;
+    return LIFT_OK;
+}
+
+lift_status lift_stamp_next_launch(uint64_t *stamps, int64_t capacity, int32_t *clock_khz)
+{
+    if (!stamps) {
+        g_stamps = nullptr;
+        g_stamp_capacity = 0;
+        return LIFT_OK;
+    }
+    if (capacity <= 0 || !aligned(stamps, 8) || !clock_khz)
+        return LIFT_EINVAL;
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    *clock_khz = khz;
+    g_stamps = stamps;
+    g_stamp_capacity = capacity;
     return LIFT_OK;
 }
 

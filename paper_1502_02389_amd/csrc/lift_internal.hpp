@@ -39,7 +39,17 @@ struct ReduceArgs {
     void *result;
     int32_t result_f64;
     int32_t interleave;  // 1: work-group b takes steps b, b + G, ... (grid-stride)
+    uint64_t *stamps;    // stamped instances only: STAMPS_PER_WG clock readings per work-group
 };
+
+// Clock readings of a stamped reduction launch, per work-group (the device's
+// constant wall clock): [0] entry, [1] streaming loop done, [2] work-group
+// tree done, [3] partial stored, [4] arrival counted, [5] end (the last
+// work-group: after the combine; the others: = [4]); [6] ids: bit 32 set in
+// the work-group that combined, bits 16-19 its XCC, bits 0-7 HW_ID[15:8]
+// (CU, shader array, shader engine); [7] unused.
+constexpr int STAMPS_PER_WG = 8;
+const void *reduce_kernel_stamped_f32(int op, int unroll);
 
 // map(mult(alpha), x) with the same head / vector / tail split.
 struct ScalArgs {

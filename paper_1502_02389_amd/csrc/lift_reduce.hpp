@@ -259,7 +259,18 @@ __device__ __forceinline__ void accumulate_scalar(LaneAcc<ACC, E> &acc, float a,
     }
 }
 
-template <class T, int OP, int ACC, int VB, int U>
+// Clock reading for the stamped instances (s_memrealtime: 100 MHz, shared
+// by all XCDs), written by thread 0 with an ordinary vector store.
+template <bool STAMP>
+__device__ __forceinline__ void stamp(const ReduceArgs &a, int k)
+{
+    if constexpr (STAMP) {
+        if (threadIdx.x == 0)
+            a.stamps[(int64_t)blockIdx.x * STAMPS_PER_WG + k] = (uint64_t)wall_clock64();
+    }
+}
+
+template <class T, int OP, int ACC, int VB, int U, bool STAMP = false>
 __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
 {
     constexpr int E = Elems<T, VB>::value;
@@ -270,6 +281,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     __shared__ ST lds_final[16];
     __shared__ int last;
 
+    stamp<STAMP>(a, 0);
     const int t = threadIdx.x;
     const int64_t B = blockDim.x;
     const char *xv = reinterpret_cast<const char *>(a.x) + a.head * T::bytes;
@@ -347,7 +359,13 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
         accumulate_scalar<T, OP, ACC, E>(acc, load_elem<T>(a.x, tail0 + t), fy);
     }
 
+    if constexpr (STAMP) {  // every load of the streaming loop has been consumed
+        __builtin_amdgcn_sched_barrier(0);
+        stamp<STAMP>(a, 1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     BT wg = block_sum<BT>(acc.value(), lds_block);
+    stamp<STAMP>(a, 2);
 
     if (gridDim.x == 1) {
         if (t == 0)
@@ -361,7 +379,22 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if constexpr (STAMP) {
+            __builtin_amdgcn_sched_barrier(0);
+            stamp<STAMP>(a, 3);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         last = arrive(reinterpret_cast<unsigned *>(a.ws), reinterpret_cast<char *>(a.ws) + WS_GROUPS);
+        if constexpr (STAMP) {  // after the arrival's atomics have returned (last depends on them)
+            __builtin_amdgcn_sched_barrier(0);
+            const uint64_t now = (uint64_t)wall_clock64();
+            a.stamps[(int64_t)blockIdx.x * STAMPS_PER_WG + 4] = now;
+            a.stamps[(int64_t)blockIdx.x * STAMPS_PER_WG + 5] = now;
+            const uint32_t xcc = __builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (3 << 11));   // XCC_ID[3:0]
+            const uint32_t hw = __builtin_amdgcn_s_getreg((4 << 0) | (8 << 6) | (7 << 11));     // HW_ID[15:8]: CU, SH, SE
+            a.stamps[(int64_t)blockIdx.x * STAMPS_PER_WG + 6] =
+                ((uint64_t)(last ? 1u : 0u) << 32) | ((uint64_t)xcc << 16) | hw;
+        }
     }
     __syncthreads();
     if (!last)
@@ -374,6 +407,10 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     if (t == 0) {
         write_result(a.result, a.result_f64, v);
         __hip_atomic_store(reinterpret_cast<unsigned *>(a.ws), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if constexpr (STAMP) {
+        __builtin_amdgcn_sched_barrier(0);
+        stamp<STAMP>(a, 5);
     }
 }
 
@@ -424,6 +461,19 @@ const void *pick_reduce(int op, int acc, int vec_bytes, int unroll)
     if (op == OP_DOT)
         return pick_acc<T, OP_DOT>(acc, vec_bytes, unroll);
     return nullptr;
+}
+
+// The stamped instances (binary32 storage and accumulation, 16-byte loads).
+template <int OP>
+const void *pick_stamped(int unroll)
+{
+    switch (unroll) {
+    case 1: return reinterpret_cast<const void *>(&reduce_kernel<F32, OP, ACC_F32, 16, 1, true>);
+    case 2: return reinterpret_cast<const void *>(&reduce_kernel<F32, OP, ACC_F32, 16, 2, true>);
+    case 4: return reinterpret_cast<const void *>(&reduce_kernel<F32, OP, ACC_F32, 16, 4, true>);
+    case 8: return reinterpret_cast<const void *>(&reduce_kernel<F32, OP, ACC_F32, 16, 8, true>);
+    default: return nullptr;
+    }
 }
 
 }  // namespace lift

@@ -114,7 +114,8 @@ SIGNATURES = {
     "lift_batch_destroy": (None, [_vp]),
     "lift_stream_read": (_i32, [_i64, _vp, _vp, _kp, _vp]),
     "lift_stream_copy": (_i32, [_i64, _vp, _vp, _kp, _vp]),
-    "lift_default_knobs": (_i32, [ctypes.c_char_p, _i32, _i32, _i64, ctypes.c_char_p, ctypes.c_int32, _kp]),
+    "lift_stamp_next_launch": (_i32, [_vp, _i64, ctypes.POINTER(ctypes.c_int32)]),
+    "lift_default_knobs": (_i32, [ctypes.c_char_p, _i32, _i32, _i64, _i64, ctypes.c_char_p, ctypes.c_int32, _kp]),
 }
 
 
@@ -212,16 +213,25 @@ def lift_stream_copy(n, x, out, knobs=None, stream=0):
     return _lib().lift_stream_copy(n, x, out, _kptr(knobs), stream)
 
 
-def lift_default_knobs(op, storage, acc, elements, arch=None, cus=0):
+def lift_default_knobs(op, storage, acc, elements, arch=None, cus=0, row_length=0):
     """(source, knobs dict) of a call without knobs: source 2 = LIFT_FORCE_CONFIG,
     1 = the tuned table, 0 = the defaults (all-zero knobs); arch None = the
-    current device.  Raises LiftError on a negative status."""
+    current device; row_length: gemv's n.  Raises LiftError on a negative
+    status."""
     k = lift_knobs()
-    st = _lib().lift_default_knobs(op.encode(), storage, acc, elements, arch.encode() if arch else None, cus,
-                                   ctypes.byref(k))
+    st = _lib().lift_default_knobs(op.encode(), storage, acc, elements, row_length, arch.encode() if arch else None,
+                                   cus, ctypes.byref(k))
     if st < 0:
         raise LiftError(st, "lift_default_knobs")
     return st, {f: getattr(k, f) for f, _ in lift_knobs._fields_}
+
+
+def lift_stamp_next_launch(stamps, capacity):
+    """Arm the stamped instance for the next asum / dot launch; returns
+    (status, clock rate in kHz)."""
+    khz = ctypes.c_int32(0)
+    st = _lib().lift_stamp_next_launch(stamps, capacity, ctypes.byref(khz) if stamps else None)
+    return st, khz.value
 
 
 def lift_status_string(status):

@@ -49,8 +49,14 @@ def bucket(elements: int) -> int:
     return int(math.floor(math.log2(elements))) if elements > 0 else 0
 
 
-def key(op: str, storage: str, acc: str, elements: int) -> str:
-    return f"{op}/{storage}/{acc}/{bucket(elements)}"
+def key(op: str, storage: str, acc: str, elements: int, row_length: int = 0) -> str:
+    """Cache key: op/storage/acc/bucket; gemv adds the bucket of its row
+    length (the lowering that wins depends on it: whether x fits in a
+    work-group's registers, how many rows share a wavefront)."""
+    k = f"{op}/{storage}/{acc}/{bucket(elements)}"
+    if op == "gemv":
+        k += f"/{bucket(row_length)}"
+    return k
 
 
 _CACHE = None
@@ -80,17 +86,18 @@ def current_device():
     return props.gcnArchName.split(":")[0], props.multi_processor_count
 
 
-def lookup(op: str, storage: str, acc: str, elements: int, device=None):
+def lookup(op: str, storage: str, acc: str, elements: int, device=None, row_length: int = 0):
     """Tuned knobs for this call shape on `device` ((arch, cus); None = the
     current GPU), or None: no entry, or the cache was tuned on another
-    device (then the library's defaults apply)."""
+    device (then the library's defaults apply).  gemv: elements = m n and
+    row_length = n."""
     data = load_cache()
     meta = data.get("device") or {}
     if device is None:
         device = current_device()
     if (meta.get("arch"), meta.get("cus")) != tuple(device):
         return None
-    ent = data["entries"].get(key(op, storage, acc, elements))
+    ent = data["entries"].get(key(op, storage, acc, elements, row_length))
     if not ent:
         return None
     return B.knobs(**ent["knobs"])
@@ -139,7 +146,9 @@ def grid(op: str, storage: str, quick: bool = False):
         for b, v, u, w in itertools.product(blocks, (4, 8, 16), (1, 2, 4), (2, 4, 8, 16, 32)):
             yield dict(block=b, vec_bytes=v, unroll=u, wg_per_cu=w)
         return
-    blocks = (256, 512) if quick else (128, 256, 512, 1024)
+    # 64 lanes: one wavefront per work-group, whose tree is the wave's
+    # butterfly alone (no LDS stage)
+    blocks = (256, 512) if quick else (64, 128, 256, 512, 1024)
     vecs = (16,) if quick else tuple(v for v in (4, 8, 16) if v >= eb)
     splits = (0, 1 << 15, 1 << 16, 1 << 17, 1 << 18) if quick else \
         (0, 1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
@@ -372,12 +381,12 @@ def main(argv=None):
                     if op == "gemv":
                         best, res = tune_one(op, storage, acc, m=shp[0], n=shp[1], quick=args.quick,
                                              log=log if args.verbose else None, space=args.space)
-                        elements = shp[0] * shp[1]
+                        elements, row_length = shp[0] * shp[1], shp[1]
                     else:
                         best, res = tune_one(op, storage, acc, elements=shp[0], quick=args.quick,
                                              log=log if args.verbose else None, space=args.space)
-                        elements = shp[0]
-                    k = key(op, storage, acc, elements)
+                        elements, row_length = shp[0], 0
+                    k = key(op, storage, acc, elements, row_length)
                     entries[k] = best
                     log(f"== {k}: best {best}")
                     for us, kn, gbs in res[: args.top]:

@@ -51,20 +51,35 @@ def test_cache_records_its_device():
 @pytest.mark.parametrize("key,ent", _entries(), ids=[k for k, _ in _entries()])
 def test_c_table_and_python_cache_agree(key, ent, monkeypatch):
     monkeypatch.delenv("LIFT_TUNE_CACHE", raising=False)
-    op, storage, acc, bucket = key.split("/")
+    op, storage, acc, bucket = key.split("/")[:4]
+    rows = [1 << int(key.split("/")[4]), (2 << int(key.split("/")[4])) - 1] if op == "gemv" else [0]
     arch, cus = _device()
     want = {f: int(ent["knobs"].get(f, 0)) for f in FIELDS}
     for elements in ([0] if op == "batch" else [1 << int(bucket), (1 << int(bucket)) + 12345,
                                                 (2 << int(bucket)) - 1]):
-        src, got = L.lift_default_knobs(op, STORAGE[storage], ACC[acc], elements, arch, cus)
-        assert src == 1 and got == want, (elements, got, want)
-        py = tune.lookup(op, storage, acc, elements, device=(arch, cus))
-        assert py is not None and _as_dict(py) == want
+        for n in rows:
+            src, got = L.lift_default_knobs(op, STORAGE[storage], ACC[acc], elements, arch, cus, row_length=n)
+            assert src == 1 and got == want, (elements, n, got, want)
+            py = tune.lookup(op, storage, acc, elements, device=(arch, cus), row_length=n)
+            assert py is not None and _as_dict(py) == want
+
+
+def test_gemv_entries_are_keyed_by_row_length():
+    # the two shapes of the paper's 8192 x 16384 gemv share m n = 2^27 but
+    # not the row length: each gets its own entry, and a row length with no
+    # entry gets the defaults
+    arch, cus = _device()
+    keys = {k for k, _ in _entries()}
+    assert {"gemv/f32/f32/27/13", "gemv/f32/f32/27/14"} <= keys
+    a = L.lift_default_knobs("gemv", L.LIFT_F32, 0, 1 << 27, arch, cus, row_length=8192)
+    b = L.lift_default_knobs("gemv", L.LIFT_F32, 0, 1 << 27, arch, cus, row_length=16384)
+    assert a[0] == b[0] == 1 and a[1] != b[1]
+    assert L.lift_default_knobs("gemv", L.LIFT_F32, 0, 1 << 27, arch, cus, row_length=64)[0] == 0
 
 
 def test_other_device_gets_defaults():
     key, ent = _entries()[0]
-    op, storage, acc, bucket = key.split("/")
+    op, storage, acc, bucket = key.split("/")[:4]
     arch, cus = _device()
     elements = 0 if op == "batch" else 1 << int(bucket)
     for other in (("gfx942", cus), (arch, cus - 1), ("gfx9500", cus)):
@@ -92,6 +107,8 @@ def test_query_rejects_bad_arguments():
         L.lift_default_knobs("asum", L.LIFT_F32, 3, 16, arch, cus)
     with pytest.raises(L.LiftError):
         L.lift_default_knobs("asum", L.LIFT_F32, 0, -1, arch, cus)
+    with pytest.raises(L.LiftError):
+        L.lift_default_knobs("gemv", L.LIFT_F32, 0, 16, arch, cus, row_length=-4)
 
 
 def _child(code, env_value):
