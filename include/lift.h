@@ -216,6 +216,22 @@ lift_status lift_dot_ex(int64_t n, lift_dtype xt, const void *x, const void *y, 
                         lift_dtype rt, void *result, void *ws, size_t ws_bytes,
                         const lift_knobs *knobs, hipStream_t stream);
 
+/* lift_dot_ex without a workspace argument, for callers that cannot
+ * allocate device memory or pass one (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The call allocates
+ * nothing: its arrival counters and per-work-group partials live in a
+ * static device array of 164,096 bytes inside the library (the workspace
+ * size of lift_workspace_bytes(), enough for the largest grid any reduction
+ * launches, so every n is accepted), one copy per device, held until the
+ * process ends.  Same arguments, results (bit for bit, for the same knobs)
+ * and errors as lift_dot_ex; the first call on a device also looks up that
+ * device's copy (LIFT_EHIP if that fails).  Every call on a device shares
+ * its copy: calls that may overlap on one device (different streams, or
+ * host threads racing on one stream) race on it and must be serialised by
+ * the caller; lift_dot_ex with distinct workspaces is the concurrent form. */
+lift_status lift_dot_ex_noalloc(int64_t n, lift_dtype xt, const void *x, const void *y, lift_acc acc,
+                                lift_dtype rt, void *result, const lift_knobs *knobs, hipStream_t stream);
+
 /* gemv with A stored as at (F32, BF16 or F16); x and y are binary32. */
 lift_status lift_gemv_ex(int64_t m, int64_t n, float alpha, lift_dtype at, const void *A,
                          int64_t lda, const float *x, float beta, float *y, lift_acc acc,

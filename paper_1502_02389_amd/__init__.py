@@ -15,6 +15,6 @@ from .lift import (  # noqa: F401
     workspace, HipEvents, Batch, GraphRun, lift_problem, lift_batch_create, lift_batch_run,
     lift_batch_capture, lift_batch_info, lift_batch_destroy, LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV,
     blackscholes, lift_blackscholes, lift_blackscholes_ex, md, lift_md, lift_md_ex,
-    lift_stream_read, lift_stream_copy, lift_default_knobs,
+    lift_stream_read, lift_stream_copy, lift_default_knobs, lift_dot_ex_noalloc,
     lift_stamp_next_launch,
 )

@@ -719,6 +719,43 @@ lift_status stream_common(bool copy, int64_t n, const float *x, float *out, cons
     return launch(kern, std::max<int64_t>(1, (nvec + chunk - 1) / chunk), k.block, &a, stream);
 }
 
+// ---- allocation-free reductions --------------------------------------------
+//
+// lift_dot_ex_noalloc keeps its arrival counters and partial slots in this
+// file-scope device array instead of a caller workspace: one copy per device,
+// zero-filled when the library's code object is loaded on it, and left with
+// its counters zeroed by every call that completes (the last work-group
+// resets them), so nothing is cleared per call.  In host code `scratch` names
+// a host-side stand-in; the device address of each device's copy comes from
+// hipGetSymbolAddress with that device current, once, and only that address
+// is handed to kernels.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)(WS_HEADER + (int64_t)MAX_WORKGROUPS * WS_SLOT);
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+lift_status static_scratch(void **out)
+{
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return LIFT_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e);
+        if (!p)
+            return LIFT_EHIP;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return LIFT_OK;
+}
+
 }  // namespace
 
 // A planned batch: one launch over the reduction tiles ([0]) and one over
@@ -1053,6 +1090,26 @@ lift_status lift_dot_ex(int64_t n, lift_dtype xt, const void *x, const void *y, 
                         const lift_knobs *knobs, hipStream_t stream)
 {
     return reduce_common(OP_DOT, n, xt, x, y, acc, rt, result, ws, ws_bytes, knobs, stream);
+}
+
+lift_status lift_dot_ex_noalloc(int64_t n, lift_dtype xt, const void *x, const void *y, lift_acc acc,
+                                lift_dtype rt, void *result, const lift_knobs *knobs, hipStream_t stream)
+{
+    lift_status st = reduce_check(OP_DOT, n, xt, x, y, acc, rt, result);
+    if (st != LIFT_OK)
+        return st;
+    Knobs checked;  // explicit knobs and the override are checked before the first HIP call
+    if (knobs && (st = resolve(knobs, DEF_REDUCE, elem_bytes(xt), &checked)) != LIFT_OK)
+        return st;
+    if (!knobs && forced_config().present && !forced_config().valid)
+        return LIFT_EINVAL;
+    static_assert(STATIC_SCRATCH_BYTES >= (size_t)(WS_HEADER + (int64_t)MAX_WORKGROUPS * WS_SLOT),
+                  "the array holds a partial for the largest grid a reduction launches");
+    void *ws = nullptr;
+    st = static_scratch(&ws);
+    if (st != LIFT_OK)
+        return st;
+    return reduce_common(OP_DOT, n, xt, x, y, acc, rt, result, ws, STATIC_SCRATCH_BYTES, knobs, stream);
 }
 
 lift_status lift_blackscholes_ex(int64_t n, const float *s, float strike, float rate, float volatility,

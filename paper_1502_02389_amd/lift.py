@@ -115,6 +115,7 @@ SIGNATURES = {
     "lift_stream_read": (_i32, [_i64, _vp, _vp, _kp, _vp]),
     "lift_stream_copy": (_i32, [_i64, _vp, _vp, _kp, _vp]),
     "lift_stamp_next_launch": (_i32, [_vp, _i64, ctypes.POINTER(ctypes.c_int32)]),
+    "lift_dot_ex_noalloc": (_i32, [_i64, _i32, _vp, _vp, _i32, _i32, _vp, _kp, _vp]),
     "lift_default_knobs": (_i32, [ctypes.c_char_p, _i32, _i32, _i64, _i64, ctypes.c_char_p, ctypes.c_int32, _kp]),
 }
 
@@ -183,6 +184,10 @@ def lift_asum_ex(n, xt, x, acc, rt, result, ws, ws_bytes, knobs=None, stream=0):
 
 def lift_dot_ex(n, xt, x, y, acc, rt, result, ws, ws_bytes, knobs=None, stream=0):
     return _lib().lift_dot_ex(n, xt, x, y, acc, rt, result, ws, ws_bytes, _kptr(knobs), stream)
+
+
+def lift_dot_ex_noalloc(n, xt, x, y, acc, rt, result, knobs=None, stream=0):
+    return _lib().lift_dot_ex_noalloc(n, xt, x, y, acc, rt, result, _kptr(knobs), stream)
 
 
 def lift_gemv_ex(m, n, alpha, at, A, lda, x, beta, y, acc, knobs=None, stream=0):

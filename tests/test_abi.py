@@ -162,6 +162,11 @@ def wsb():
     (lambda: L.lift_stream_copy(8, X, Y + 4), L.LIFT_EINVAL),                        # out not 16-aligned
     (lambda: L.lift_stream_copy(8, X, X + 16), L.LIFT_EINVAL),                       # overlap
     (lambda: L.lift_stream_copy(0, X, Y), L.LIFT_OK),                                # empty: no-op
+    (lambda: L.lift_dot_ex_noalloc(-1, 0, X, Y, 0, 0, R), L.LIFT_EINVAL),            # the no-workspace dot:
+    (lambda: L.lift_dot_ex_noalloc(8, 0, X, 0, 0, 0, R), L.LIFT_EINVAL),             # same checks, before
+    (lambda: L.lift_dot_ex_noalloc(8, 0, X, Y, 0, 0, X + 4), L.LIFT_EINVAL),         # any HIP call
+    (lambda: L.lift_dot_ex_noalloc(8, 7, X, Y, 0, 0, R), L.LIFT_EINVAL),
+    (lambda: L.lift_dot_ex_noalloc(8, 0, X, Y, 0, 0, R, B.knobs(unroll=3)), L.LIFT_EINVAL),
 ])
 def test_rejects_before_any_hip_call(case, expect):
     assert case() == expect
