@@ -19,9 +19,11 @@ its kernels use -- and evaluates it with the patterns of ``patterns.py``:
       o split-(C/B) o reorder-stride^B
     ) o split-C o asVector-E                    (C vectors per work-group)
 
-followed, when there is more than one work-group, by the same lane / wave /
-work-group tree over the work-group partials (lane t folds partials t, t+B,
-...).  The head and tail scalars are added to component 0 of lanes of the
+followed, when there is more than one work-group, by the final combine of
+the work-group partials: lane t of one wavefront folds partials t, t+64, ...,
+then the wave's butterfly (the batched form combines a problem's tile
+partials over a whole work-group: lane t of B folds t, t+B, ..., then the
+work-group tree).  The head and tail scalars are added to component 0 of lanes of the
 first and last work-group.
 
 ``evaluate(x, shape, add)`` runs the expression with a caller-given binary
@@ -58,6 +60,7 @@ class Shape:
     grid: int        # work-groups G
     step: int = 0    # B * unroll vectors: with interleave, work-group b takes
     interleave: bool = False   # steps b, b + G, ... instead of one chunk
+    final_lanes: int = 64      # lanes of the final combine of the G partials
 
     @property
     def tail(self) -> int:
@@ -65,12 +68,16 @@ class Shape:
 
 
 def launch_shape(n: int, elem_bytes: int, vec_bytes: int, block: int, unroll: int, split: int,
-                 misalign_elems: int = 0, max_workgroups: int = 8192, interleave: bool = False) -> Shape:
+                 misalign_elems: int = 0, max_workgroups: int = 8192, interleave: bool = False,
+                 final_lanes: int = 64) -> Shape:
     """The documented launch rules for an explicit split (elements per chunk).
 
     ``misalign_elems``: how many elements past a vec_bytes boundary x starts.
     ``interleave``: the work-groups (as many as the split gives) take steps
     of block * unroll vectors round-robin instead of one chunk each.
+    ``final_lanes``: lanes that fold the work-group partials at the end (one
+    wavefront in the per-call kernels; a whole work-group in the batched
+    form's per-problem combine).
     """
     e = vec_bytes // elem_bytes
     head = 0 if misalign_elems % e == 0 else e - misalign_elems % e
@@ -82,7 +89,7 @@ def launch_shape(n: int, elem_bytes: int, vec_bytes: int, block: int, unroll: in
     if -(-nvec // chunk) > max_workgroups:
         chunk = -(-(-(-nvec // max_workgroups)) // step) * step
     grid = max(1, -(-nvec // chunk))
-    return Shape(n, head, e, nvec, block, chunk, grid, step, interleave)
+    return Shape(n, head, e, nvec, block, chunk, grid, step, interleave, final_lanes)
 
 
 def _pairwise(values, add):
@@ -188,11 +195,13 @@ def _launch(vectors, zero_item, head, tail0, s: Shape, lane_step, scalar_step, a
         partials.append(_block_tree(lane_vals, add))                # toLocal tree
     if G == 1:
         return partials[0]
-    # final reduce-seq o join over the work-group partials, by one work-group:
-    # lane t folds partials t, t+B, ... (from 0), then the same tree
-    padded = partials + [zero] * (-(-G // B) * B - G)
+    # final reduce-seq o join over the work-group partials, by F lanes (one
+    # wavefront, or a work-group): lane t folds partials t, t+F, ... (from
+    # 0), then the tree over the lanes
+    F = s.final_lanes
+    padded = partials + [zero] * (-(-G // F) * F - G)
     lane_vals = []
-    for row in P.split(len(padded) // B)(P.reorder_stride(B)(padded)):
+    for row in P.split(len(padded) // F)(P.reorder_stride(F)(padded)):
         acc = zero
         for p in row:
             acc = add(acc, p)

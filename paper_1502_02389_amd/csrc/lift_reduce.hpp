@@ -13,9 +13,10 @@
 // term(a) = |a| (asum) or a_x * a_y (dot, zip fused into the load).  The
 // final reduce-seq o join runs in the same launch: every work-group stores
 // its partial, then counts in on agent-scope arrival counters (two levels,
-// see arrive()); the one that arrives last folds all partials in
-// work-group order and writes the result, then resets the counter for the
-// next call.  No float atomics
+// see arrive()); in the one that arrives last, one wavefront folds all
+// partials (lane t: partials t, t + 64, ...; then the wave butterfly) and
+// writes the result, then resets the counter for the next call.  No float
+// atomics
 // and no inter-work-group waiting, so the result is deterministic and the
 // grid always drains.
 //
@@ -278,8 +279,6 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     using BT = typename BlockT<ACC>::type;
     using ST = typename SlotT<ACC>::type;
     __shared__ BT lds_block[16];
-    __shared__ ST lds_final[16];
-    __shared__ int last;
 
     stamp<STAMP>(a, 0);
     const int t = threadIdx.x;
@@ -373,7 +372,12 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
         return;
     }
 
+    // The rest is wave 0's: the other waves are done once the tree has their
+    // values (block_sum ends with a barrier).
+    if (t >= 64)
+        return;
     char *slots = reinterpret_cast<char *>(a.ws) + WS_HEADER;  // 16-byte slots
+    int last = 0;
     if (t == 0) {
         store_coherent(slots + (int64_t)blockIdx.x * WS_SLOT, to_slot<ACC>(wg));
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -384,7 +388,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
             stamp<STAMP>(a, 3);
             __builtin_amdgcn_sched_barrier(0);
         }
-        last = arrive(reinterpret_cast<unsigned *>(a.ws), reinterpret_cast<char *>(a.ws) + WS_GROUPS);
+        last = arrive(reinterpret_cast<unsigned *>(a.ws), reinterpret_cast<char *>(a.ws) + WS_GROUPS) ? 1 : 0;
         if constexpr (STAMP) {  // after the arrival's atomics have returned (last depends on them)
             __builtin_amdgcn_sched_barrier(0);
             const uint64_t now = (uint64_t)wall_clock64();
@@ -393,17 +397,30 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
             const uint32_t xcc = __builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (3 << 11));   // XCC_ID[3:0]
             const uint32_t hw = __builtin_amdgcn_s_getreg((4 << 0) | (8 << 6) | (7 << 11));     // HW_ID[15:8]: CU, SH, SE
             a.stamps[(int64_t)blockIdx.x * STAMPS_PER_WG + 6] =
-                ((uint64_t)(last ? 1u : 0u) << 32) | ((uint64_t)xcc << 16) | hw;
+                ((uint64_t)(unsigned)last << 32) | ((uint64_t)xcc << 16) | hw;
         }
     }
-    __syncthreads();
+    last = __builtin_amdgcn_readfirstlane(last);  // lane 0's decision, for the whole wave
     if (!last)
         return;
 
+    // The final reduce-seq o join, by one wavefront: lane t folds partials
+    // t, t + 64, t + 128, ... in that order (COMBINE_LOADS loads in flight),
+    // then the wave butterfly; no barrier on this path.
+    constexpr int COMBINE_LOADS = 8;
+    const int64_t G = gridDim.x;
     ST v = zero_of<ST>();
-    for (int64_t i = t; i < gridDim.x; i += B)
-        v = merge(v, load_coherent<ST>(slots + i * WS_SLOT));
-    v = block_sum<ST>(v, lds_final);
+    for (int64_t base = 0; base < G; base += 64 * COMBINE_LOADS) {
+        ST p[COMBINE_LOADS];
+#pragma unroll
+        for (int k = 0; k < COMBINE_LOADS; ++k)
+            p[k] = load_coherent<ST>(slots + min(base + t + 64 * k, G - 1) * WS_SLOT);
+#pragma unroll
+        for (int k = 0; k < COMBINE_LOADS; ++k)
+            if (base + t + 64 * k < G)
+                v = merge(v, p[k]);
+    }
+    v = wave_sum(v);
     if (t == 0) {
         write_result(a.result, a.result_f64, v);
         __hip_atomic_store(reinterpret_cast<unsigned *>(a.ws), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -330,7 +330,7 @@ def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
             mis = (xd.data_ptr() % vb) // eb
             same = kind == "asum" or pr[2].data_ptr() % vb == xd.data_ptr() % vb
             shape = LW.launch_shape(n, eb, vb if same else eb, B, U, split, misalign_elems=mis if same else 0,
-                                    max_workgroups=1 << 30)
+                                    max_workgroups=1 << 30, final_lanes=B)
             xs = [float(v) for v in x.float().numpy()]
             if kind == "asum":
                 pred = LW.evaluate(xs, shape, add=F32B.add, absval=abs, zero=0.0)
