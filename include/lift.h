@@ -53,7 +53,15 @@
  *             floating-point sums differently (the paper's reduction rule,
  *             Fig. 3d, allows any partition); integer-valued inputs whose
  *             partial sums stay below 2^24 in magnitude give identical
- *             results under every knob set.
+ *             results under every knob set.  The cross-work-group combine
+ *             relies on gfx950's memory behaviour rather than on fences:
+ *             partials are written with agent-scope atomic stores (which the
+ *             hardware writes through past the XCD-private L2), a work-group
+ *             counts in on the arrival counters only after its store has
+ *             completed (a wait on the store, not a release fence, which
+ *             would write back the whole L2), and the combining work-group
+ *             reads the partials with agent-scope atomic loads (which miss
+ *             the L2).  Built and tested for gfx950 only.
  */
 #ifndef LIFT_H
 #define LIFT_H
@@ -309,11 +317,11 @@ lift_status lift_md_ex(int64_t n, const float *pos, int64_t k, const int32_t *nb
  * per-call form with one row per wavefront): with vector loads where A's
  * rows start on vec_bytes boundaries and x is aligned to
  * min(vec_bytes / element size * 4, 16) bytes; else, for vec_bytes of at
- * most 8, rows of at least 64 * unroll * E columns (E = vec_bytes / element
- * size) and E copies of x, each padded to a multiple of 4 floats, fitting in
+ * most 8, rows of at least 64 * E columns (E = vec_bytes / element size)
+ * and E copies of x, each padded to a multiple of 4 floats, fitting in
  * 16320 floats of LDS, each row from its own start: scalars up to its first
- * vec_bytes boundary, then vectors, then the scalar tail; else with element
- * loads. */
+ * vec_bytes boundary, then vectors, then the scalar tail (a wavefront takes
+ * two rows E apart, which start alike); else with element loads. */
 typedef enum lift_kind {
     LIFT_KIND_ASUM = 0,
     LIFT_KIND_DOT = 1,
@@ -413,11 +421,17 @@ lift_status lift_time_next_launch(hipEvent_t start, hipEvent_t stop);
  * its arrival is counted, and at its end (the combining work-group: after
  * the combine), then ids (bit 32: the work-group that combined; bits 16-19:
  * its XCC; bits 0-7: HW_ID[15:8], CU / shader array / shader engine), then
- * one unused word.  *clock_khz receives the clock's rate.  One-shot; that
+ * one unused word.  If the next call is lift_batch_run instead (binary32
+ * accumulation, F32 or BF16 storage), its gemv launch runs the stamped
+ * instance of its kernel, which writes 4 words per gemv tile (in the order
+ * of the batch's tile table; `capacity` counts tiles): the clock when a
+ * work-group takes the tile and when it is done with it, the tile's problem
+ * index (high 32 bits) and row count (low 32), and ids (high 32 bits, as
+ * above) with the work-group (low 32).  *clock_khz receives the clock's rate.  One-shot; that
  * launch fails with LIFT_EUNSUPPORTED for another storage, accumulation or
- * vector width and LIFT_EINVAL if its grid exceeds `capacity` (the hook is
- * cleared either way).  stamps == NULL disarms it.  LIFT_EINVAL: capacity
- * <= 0, stamps not 8-byte aligned or clock_khz NULL. */
+ * vector width and LIFT_EINVAL if its grid (tile count) exceeds `capacity`
+ * (the hook is cleared either way).  stamps == NULL disarms it.
+ * LIFT_EINVAL: capacity <= 0, stamps not 8-byte aligned or clock_khz NULL. */
 lift_status lift_stamp_next_launch(uint64_t *stamps, int64_t capacity, int32_t *clock_khz);
 
 /* The knobs a call with knobs == NULL would run with on a device of

@@ -771,6 +771,7 @@ struct lift_batch {
     const void *kern[2] = {nullptr, nullptr};
     BatchArgs args[2]{};
     hipEvent_t ev[2] = {nullptr, nullptr};  // inner ends of a timed two-launch run
+    int storage = 0, acc = 0, vb = 0, unroll = 0;  // for the stamped gemv instance
 };
 
 namespace {
@@ -882,10 +883,10 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
             }
             const int64_t xalign = std::min<int64_t>(e * 4, 16);
             p.vec = q.n > 0 && aligned(q.a, vb) && (q.lda * eb) % vb == 0 && aligned(q.b, xalign);
-            // rows with heads against shifted copies of x in LDS, for rows that
-            // fill a step of the row-pair form (shorter ones keep element loads,
+            // rows with heads against shifted copies of x in LDS, for rows with
+            // at least one vector per lane (shorter ones keep element loads,
             // two rows per wavefront)
-            if (!p.vec && e > 1 && vb <= 8 && q.n >= 64 * k.unroll * e && e * ((q.n + 3) / 4 * 4) <= BATCH_LDS_X)
+            if (!p.vec && e > 1 && vb <= 8 && q.n >= 64 * e && e * ((q.n + 3) / 4 * 4) <= BATCH_LDS_X)
                 p.vec = 2;
             p.nvec = p.vec == 1 ? q.n / e : q.n;
             int64_t rows = std::max<int64_t>(1, k.split / std::max<int64_t>(1, q.n));
@@ -983,6 +984,10 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
         }
     }
     b->device = dev;
+    b->storage = storage;
+    b->acc = acc;
+    b->vb = vb;
+    b->unroll = k.unroll;
     b->nprobs = count;
     b->bytes = bytes;
     b->block = k.block;
@@ -1283,6 +1288,22 @@ lift_status lift_batch_run(lift_batch *b, hipStream_t stream)
     // pair of events fills the other ends when there are two launches).
     const hipEvent_t t0 = g_time_start, t1 = g_time_stop;
     g_time_start = g_time_stop = nullptr;
+    // an armed stamp hook takes the gemv launch's stamped instance (one-shot)
+    const void *gemv_kern = b->kern[1];
+    uint64_t *stamps = nullptr;
+    if (g_stamps) {
+        stamps = g_stamps;
+        const int64_t cap = g_stamp_capacity;
+        g_stamps = nullptr;
+        if (b->acc != LIFT_ACC_F32 || (b->storage != LIFT_F32 && b->storage != LIFT_BF16))
+            return LIFT_EUNSUPPORTED;
+        if (b->ntiles[1] > cap)
+            return LIFT_EINVAL;
+        gemv_kern = b->storage == LIFT_F32 ? batch_gemv_stamped_f32(b->vb, b->unroll)
+                                           : batch_gemv_stamped_bf16(b->vb, b->unroll);
+        if (!gemv_kern)
+            return LIFT_EUNSUPPORTED;
+    }
     const int first = b->ntiles[0] > 0 ? 0 : 1, last = b->ntiles[1] > 0 ? 1 : 0;
     for (int kd = first; kd <= last; ++kd) {
         if (b->ntiles[kd] == 0)
@@ -1292,7 +1313,9 @@ lift_status lift_batch_run(lift_batch *b, hipStream_t stream)
             g_time_stop = kd == last ? t1 : b->ev[0];
         }
         BatchArgs a = b->args[kd];
-        lift_status st = launch(b->kern[kd], b->grid[kd], b->block, &a, stream);
+        if (kd == 1)
+            a.stamps = stamps;
+        lift_status st = launch(kd == 1 ? gemv_kern : b->kern[kd], b->grid[kd], b->block, &a, stream);
         if (st != LIFT_OK) {
             g_time_start = g_time_stop = nullptr;
             return st;

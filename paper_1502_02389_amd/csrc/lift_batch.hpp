@@ -120,68 +120,96 @@ __device__ __forceinline__ void gemv_tile(const BatchProblem &p, const BatchTile
         gemv_row_group<T, ACC, VB, R, U>(p.a, x, y, end, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
 }
 
-// Rows [begin, begin + len) of a gemv problem whose x fits in `xl` (LDS):
-// the work-group copies x there once per tile, then each wavefront takes row
-// pairs as in gemv_tile, reading x from LDS instead of the cache (re-reading
-// x from the cache for every row pair limits the wavefront form; with 16-bit
-// A, x is twice A's bytes).  The arithmetic is gemv_row_group's, so both
-// forms give the same bits.  All threads of the work-group must call this
-// (it has barriers).
-template <class T, int ACC, int VB, int U>
-__device__ __forceinline__ void gemv_tile_lx(const BatchProblem &p, const BatchTile &tl, float *xl)
+// x (n >= 1 floats) into LDS: E copies, copy h at h * stride holding
+// x[j + h] at j (one plain copy when E is 1).  Each thread issues its K
+// loads of a round (at clamped, in-range indices) before it stores any of
+// them, so staging costs one memory round trip per K * blockDim.x floats,
+// not one per blockDim.x.  The caller places the barrier.
+template <int E>
+__device__ __forceinline__ void stage_x(const float *x, int64_t n, float *xl, int64_t stride)
 {
-    constexpr int R = 2;
-    const float *x = reinterpret_cast<const float *>(p.b);
-    for (int64_t i = threadIdx.x; i < p.n; i += blockDim.x)
-        xl[i] = x[i];
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = blockDim.x >> 6;
-    float *y = reinterpret_cast<float *>(p.out);
-    const int64_t end = tl.begin + tl.len;
-    for (int64_t r = tl.begin + (threadIdx.x >> 6) * R; r < end; r += waves * R)
-        gemv_row_group<T, ACC, VB, R, U>(p.a, xl, y, end, p.n, p.lda, p.nvec, p.alpha, p.beta, r, lane);
-    __syncthreads();  // every wave is done with xl before the next tile rewrites it
+    constexpr int K = 8;
+    const int64_t B = blockDim.x;
+    for (int64_t j0 = threadIdx.x; j0 < n; j0 += K * B) {
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            v[k] = x[min(j0 + k * B, n - 1)];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t j = j0 + k * B;
+            if (j < n) {
+#pragma unroll
+                for (int h = 0; h < E; ++h)
+                    if (j >= h)
+                        xl[h * stride + j - h] = v[k];
+            }
+        }
+    }
 }
 
-// Rows r0 .. r0 + R - 1 of a gemv problem whose rows do not all start on a
-// VB boundary, by one wavefront (rows from `end` on are read at a clamped
-// index and not written).  Each row has its own head of fewer than E
-// columns up to its first vector boundary, whole vectors from there (the x
-// vectors they meet are read from the copy of x shifted by that head, xl +
-// head * stride, which holds x[j + head] at j), and its scalar tail.  Lane
-// t folds vectors t, t + 64, ... of each row as in gemv_row_group, then
-// adds its head column (t < head) and its tail column to component 0: the
-// order of the low-level dot expression with a misaligned start, row by
-// row.  The rows' vector counts may differ by one; x is read from LDS after
-// the loads are issued, so it holds no registers across their wait.
+// Rows r0, r0 + rstep, ..., r0 + (R - 1) rstep of a gemv problem, by one
+// wavefront, with x in LDS.  The R rows must start at the same offset
+// inside a VB-byte vector: rows of a pitch that is a multiple of VB (any
+// rstep; then every head is empty), or rstep a multiple of E = VB / element
+// size; so they share one head length, one vector count and one copy of x,
+// and each x read serves all R rows.  A row from `end` on is replaced by row
+// r0 (computed, not written).  Each row: a head of fewer than E columns up
+// to its first vector boundary, whole vectors from there (the x vectors they
+// meet are read from the copy of x shifted by the head, xl + head * stride,
+// which holds x[j + head] at j), and its scalar tail.  Lane t folds vectors
+// t, t + 64, ... as in gemv_row_group, then adds its head column (t < head)
+// and its tail column to component 0: the order of the low-level dot
+// expression with a misaligned start (gemv_row_group's order when there is
+// no head), row by row.
 template <class T, int ACC, int VB, int R, int UR>
-__device__ __forceinline__ void gemv_rows_skewed(const BatchProblem &p, int64_t r0, int64_t end, const float *xl,
-                                                 int64_t stride, int lane)
+__device__ __forceinline__ void gemv_rows_phase(const BatchProblem &p, int64_t r0, int64_t rstep, int64_t end,
+                                                const float *xl, int64_t stride, int lane)
 {
     constexpr int E = Elems<T, VB>::value;
     using V = typename Vec<VB>::type;
     float *y = reinterpret_cast<float *>(p.out);
     const char *row[R], *body[R];
-    const float *xs[R];
-    int64_t head[R], nvec[R];
     float yold[R];
-    int64_t nmin = INT64_MAX;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        yold[r] = prefetch_y(y, r0 + r, end, p.beta);
-        row[r] = reinterpret_cast<const char *>(p.a) + min(r0 + r, end - 1) * p.lda * T::bytes;
-        head[r] = min((int64_t)__builtin_amdgcn_readfirstlane(
-                          (int)(((VB - (uintptr_t)row[r] % VB) % VB) / T::bytes)), p.n);
-        nvec[r] = (p.n - head[r]) / E;
-        nmin = min(nmin, nvec[r]);
-        body[r] = row[r] + head[r] * T::bytes;
-        xs[r] = xl + head[r] * stride;
+        const int64_t ri = r0 + r * rstep;
+        yold[r] = prefetch_y(y, ri, end, p.beta);
+        row[r] = reinterpret_cast<const char *>(p.a) + (ri < end ? ri : r0) * p.lda * T::bytes;
     }
+    const int64_t head = min((int64_t)__builtin_amdgcn_readfirstlane(
+                                 (int)(((VB - (uintptr_t)row[0] % VB) % VB) / T::bytes)), p.n);
+    const int64_t nvec = (p.n - head) / E;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        body[r] = row[r] + head * T::bytes;
+    const float *xs = xl + head * stride;
+    // the head and tail columns are read now, so their loads overlap the
+    // vectors' instead of costing a dependent round trip at the end; they
+    // are added after the vectors, as the expression orders them
+    // (loaded at clamped, in-range columns without a branch, so no load
+    // waits on its own; decoded and selected at the end)
+    const int64_t tail0 = head + nvec * E;
+    const bool has_head = lane < head, has_tail = tail0 + lane < p.n;
+    const int64_t hcol = min((int64_t)lane, p.n - 1), tcol = min(tail0 + lane, p.n - 1);
+    using Raw = typename T::raw;
+    Raw hraw[R], traw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        hraw[r] = reinterpret_cast<const Raw *>(row[r])[hcol];
+        traw[r] = reinterpret_cast<const Raw *>(row[r])[tcol];
+    }
+    const float hx = xl[hcol], tx = xl[tcol];
 
     RowAcc<ACC, E> acc[R];
     int64_t base = 0;
-    for (; base + 64 * UR <= nmin; base += 64 * UR) {
+    for (; base + 64 * UR <= nvec; base += 64 * UR) {
+        // x from LDS is read together with the row loads, so its latency
+        // hides behind theirs
+        float xf[UR][E];
+#pragma unroll
+        for (int k = 0; k < UR; ++k)
+            load_x<E>(xs, base + lane + 64 * k, xf[k]);
         V va[R][UR];
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -190,96 +218,122 @@ __device__ __forceinline__ void gemv_rows_skewed(const BatchProblem &p, int64_t 
                 va[r][k] = load_stream<VB>(body[r], base + lane + 64 * k);
         loads_in_flight();
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int k = 0; k < UR; ++k) {
 #pragma unroll
-            for (int k = 0; k < UR; ++k) {
-                float xf[E], af[E];
-                load_x<E>(xs[r], base + lane + 64 * k, xf);
+            for (int r = 0; r < R; ++r) {
+                float af[E];
                 decode<T, VB>(va[r][k], af);
-                acc[r].add(af, xf);
+                acc[r].add(af, xf[k]);
             }
+        }
     }
-    // the rest of every row (vector counts may differ by one, so a row may
-    // need a last step the other does not): clamped indices keep every load
-    // in its row; the vectors past a row's end become zeros
-    for (; base < nvec[0] || (R > 1 && base < nvec[R - 1]); base += 64 * UR) {
+    if (base < nvec) {
+        // the last, partial step: clamped indices keep every load in its row;
+        // the vectors past the row's end become zeros
         V va[R][UR];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int k = 0; k < UR; ++k)
-                va[r][k] = load_stream<VB>(body[r], max(min(base + lane + 64 * k, nvec[r] - 1), (int64_t)0));
+                va[r][k] = load_stream<VB>(body[r], min(base + lane + 64 * k, nvec - 1));
         loads_in_flight();
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int k = 0; k < UR; ++k) {
+            const int64_t v = min(base + lane + 64 * k, nvec - 1);
+            const bool in = base + lane + 64 * k < nvec;
+            float xf[E];
+            load_x<E>(xs, v, xf);
 #pragma unroll
-            for (int k = 0; k < UR; ++k) {
-                const int64_t v = max(min(base + lane + 64 * k, nvec[r] - 1), (int64_t)0);
-                const bool in = base + lane + 64 * k < nvec[r];
-                float xf[E], af[E];
-                load_x<E>(xs[r], v, xf);
+            for (int e = 0; e < E; ++e)
+                xf[e] = in ? xf[e] : 0.f;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float af[E];
                 decode<T, VB>(va[r][k], af);
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    xf[e] = in ? xf[e] : 0.f;
+                for (int e = 0; e < E; ++e)
                     af[e] = in ? af[e] : 0.f;
-                }
                 acc[r].add(af, xf);
             }
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (lane < head[r])
-            acc[r].add_scalar(load_elem<T>(row[r], lane), xl[lane]);
-        const int64_t tail0 = head[r] + nvec[r] * E;
-        if (tail0 + lane < p.n)
-            acc[r].add_scalar(load_elem<T>(row[r], tail0 + lane), xl[tail0 + lane]);
+        if (has_head)
+            acc[r].add_scalar(decode_raw<T>(hraw[r]), hx);
+        if (has_tail)
+            acc[r].add_scalar(decode_raw<T>(traw[r]), tx);
     }
 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+        const int64_t ri = r0 + r * rstep;
         if constexpr (ACC == ACC_F64) {
             double d = wave_sum((double)acc[r].value());
-            if (lane == 0 && r0 + r < end) {
+            if (lane == 0 && ri < end) {
                 double by = p.beta == 0.f ? 0.0 : (double)p.beta * (double)yold[r];
-                y[r0 + r] = (float)((double)p.alpha * d + by);
+                y[ri] = (float)((double)p.alpha * d + by);
             }
         } else if constexpr (ACC == ACC_COMP) {
             Pair q = wave_sum(acc[r].value());
-            if (lane == 0 && r0 + r < end)
-                store_row_y<ACC>(y, r0 + r, p.alpha, p.beta, q.s + q.c, yold[r]);
+            if (lane == 0 && ri < end)
+                store_row_y<ACC>(y, ri, p.alpha, p.beta, q.s + q.c, yold[r]);
         } else {
             float d = wave_sum(acc[r].value());
-            if (lane == 0 && r0 + r < end)
-                store_row_y<ACC>(y, r0 + r, p.alpha, p.beta, d, yold[r]);
+            if (lane == 0 && ri < end)
+                store_row_y<ACC>(y, ri, p.alpha, p.beta, d, yold[r]);
         }
     }
 }
 
+// Rows [begin, begin + len) of a gemv problem whose rows start on vector
+// boundaries (or are read element by element) and whose x fits in `xl`
+// (LDS): the work-group copies x there once per tile, then each wavefront
+// takes row pairs as in gemv_tile, reading x from LDS instead of the cache
+// (re-reading x from the cache for every row pair limits the wavefront form;
+// with 16-bit A, x is twice A's bytes).  The arithmetic is gemv_row_group's,
+// so both forms give the same bits.  All threads of the work-group must call
+// this (it has barriers).
+template <class T, int ACC, int VB, int U>
+__device__ __forceinline__ void gemv_tile_lx(const BatchProblem &p, const BatchTile &tl, float *xl)
+{
+    constexpr int R = 2;
+    if (p.n > 0)
+        stage_x<1>(reinterpret_cast<const float *>(p.b), p.n, xl, 0);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = blockDim.x >> 6;
+    const int64_t end = tl.begin + tl.len;
+    // rows start on a vector boundary (or VB is the element size): no heads,
+    // the plain copy of x serves every row
+    for (int64_t r = tl.begin + (threadIdx.x >> 6) * R; r < end; r += waves * R)
+        gemv_rows_phase<T, ACC, VB, R, U>(p, r, 1, end, xl, 0, lane);
+    __syncthreads();  // every wave is done with xl before the next tile rewrites it
+}
+
 // Rows [begin, begin + len) of a gemv problem with row heads (vec == 2): the
 // work-group writes the E shifted copies of x into `xl` (copy h at h *
-// stride holds x[j + h] for j < n - h), then each wavefront takes row
-// pairs begin + 2w, begin + 2w + 2W, ....  All threads of the work-group
-// must call this (it has barriers).
+// stride holds x[j + h] for j < n - h), then each wavefront takes pairs of
+// rows E apart, which start at the same offset inside a vector: pair q is
+// rows begin + 2E (q / E) + q % E and E rows further, wavefront w taking
+// pairs w, w + W, ....  All threads of the work-group must call this (it
+// has barriers).
 template <class T, int ACC, int VB, int U>
 __device__ __forceinline__ void gemv_tile_skew(const BatchProblem &p, const BatchTile &tl, float *xl)
 {
     constexpr int E = Elems<T, VB>::value;
     const int64_t stride = (p.n + 3) & ~(int64_t)3;   // E * stride <= BATCH_LDS_X (planner)
-    const float *x = reinterpret_cast<const float *>(p.b);
-    for (int64_t j = threadIdx.x; j < p.n; j += blockDim.x) {
-        const float v = x[j];
-#pragma unroll
-        for (int h = 0; h < E; ++h)
-            if (j >= h)
-                xl[h * stride + j - h] = v;
-    }
+    stage_x<E>(reinterpret_cast<const float *>(p.b), p.n, xl, stride);   // n >= 64 E (planner)
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t waves = blockDim.x >> 6;
     const int64_t end = tl.begin + tl.len;
-    for (int64_t r = tl.begin + (threadIdx.x >> 6) * 2; r < end; r += waves * 2)
-        gemv_rows_skewed<T, ACC, VB, 2, U>(p, r, end, xl, stride, lane);
+    const int64_t pairs = (tl.len + 2 * E - 1) / (2 * E) * E;
+    for (int64_t q = threadIdx.x >> 6; q < pairs; q += waves) {
+        const int64_t r0 = tl.begin + 2 * E * (q / E) + q % E;
+        if (r0 < end)   // wave-uniform
+            gemv_rows_phase<T, ACC, VB, 2, U>(p, r0, E, end, xl, stride, lane);
+    }
     __syncthreads();  // every wave is done with xl before the next tile rewrites it
 }
 
@@ -372,7 +426,7 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
 // the cache; rows with heads (vec == 2, vectors of at most 8 bytes) go one
 // per wavefront against shifted copies of x.  Same loop discipline as
 // batch_kernel.
-template <class T, int ACC, int VB, int U>
+template <class T, int ACC, int VB, int U, bool STAMP = false>
 __global__ void __launch_bounds__(512) batch_gemv_kernel(BatchArgs a)
 {
     constexpr int EB = T::bytes;  // element-wise loads for unaligned problems
@@ -383,6 +437,16 @@ __global__ void __launch_bounds__(512) batch_gemv_kernel(BatchArgs a)
     int ti = blockIdx.x;  // the grid never exceeds the tile count
     while (ti < a.ntiles) {
         const BatchTile tl = a.tiles[ti];
+        if constexpr (STAMP) {
+            if (t == 0) {
+                const uint32_t xcc = __builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (3 << 11));   // XCC_ID[3:0]
+                const uint32_t hw = __builtin_amdgcn_s_getreg((4 << 0) | (8 << 6) | (7 << 11));     // HW_ID[15:8]
+                a.stamps[(int64_t)ti * STAMPS_PER_TILE + 0] = (uint64_t)wall_clock64();
+                a.stamps[(int64_t)ti * STAMPS_PER_TILE + 2] = ((uint64_t)(uint32_t)tl.problem << 32) | (uint32_t)tl.len;
+                a.stamps[(int64_t)ti * STAMPS_PER_TILE + 3] =
+                    ((uint64_t)((xcc << 16) | hw) << 32) | (uint32_t)blockIdx.x;
+            }
+        }
         const BatchProblem p = a.probs[tl.problem];
         const int vec = __builtin_amdgcn_readfirstlane(p.vec);
         const int in_lds = __builtin_amdgcn_readfirstlane((int)(p.n <= BATCH_LDS_X));
@@ -399,6 +463,11 @@ __global__ void __launch_bounds__(512) batch_gemv_kernel(BatchArgs a)
                 gemv_tile<T, ACC, VB, U>(p, tl);
             else
                 gemv_tile<T, ACC, EB, U>(p, tl);
+        }
+        if constexpr (STAMP) {  // every wave is done with the tile (its stores issued)
+            __syncthreads();
+            if (t == 0)
+                a.stamps[(int64_t)ti * STAMPS_PER_TILE + 1] = (uint64_t)wall_clock64();
         }
         ti = fetch_tile(&a.counters[0], &s_tile);
     }
@@ -443,6 +512,30 @@ const void *pick_batch(int acc, int vec_bytes, int unroll, bool gemv)
     case ACC_F32: return batch_pick_vec<T, ACC_F32>(vec_bytes, unroll, gemv);
     case ACC_COMP: return batch_pick_vec<T, ACC_COMP>(vec_bytes, unroll, gemv);
     case ACC_F64: return batch_pick_vec<T, ACC_F64>(vec_bytes, unroll, gemv);
+    default: return nullptr;
+    }
+}
+
+// The stamped gemv-tile instances (binary32 accumulation).
+template <class T, int VB>
+const void *pick_batch_gemv_stamped_unroll(int unroll)
+{
+    switch (unroll) {
+    case 1: return reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, 1, true>);
+    case 2: return reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, 2, true>);
+    case 4: return reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, 4, true>);
+    case 8: return reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, 8, true>);
+    default: return nullptr;
+    }
+}
+
+template <class T>
+const void *pick_batch_gemv_stamped(int vec_bytes, int unroll)
+{
+    switch (vec_bytes) {
+    case 4: return pick_batch_gemv_stamped_unroll<T, 4>(unroll);
+    case 8: return pick_batch_gemv_stamped_unroll<T, 8>(unroll);
+    case 16: return pick_batch_gemv_stamped_unroll<T, 16>(unroll);
     default: return nullptr;
     }
 }

@@ -108,14 +108,21 @@ __device__ __forceinline__ void decode(const typename Vec<VB>::type &v, float *o
     }
 }
 
+// One stored element of storage T (its raw bits), decoded.
+template <class T>
+__device__ __forceinline__ float decode_raw(typename T::raw v)
+{
+    if constexpr (T::bytes == 4)
+        return bits_to_float(v);
+    else
+        return Decode<T>::half(v);
+}
+
 // Scalar element i of storage T, decoded.
 template <class T>
 __device__ __forceinline__ float load_elem(const void *base, int64_t i)
 {
-    if constexpr (T::bytes == 4)
-        return bits_to_float(reinterpret_cast<const uint32_t *>(base)[i]);
-    else
-        return Decode<T>::half(reinterpret_cast<const uint16_t *>(base)[i]);
+    return decode_raw<T>(reinterpret_cast<const typename T::raw *>(base)[i]);
 }
 
 // ---------------------------------------------------------------- error-free sums

@@ -145,7 +145,17 @@ struct BatchArgs {
     char *slots;
     int64_t ntiles;
     int32_t result_f64;
+    uint64_t *stamps;     // stamped gemv instances only: STAMPS_PER_TILE words per tile
 };
+
+// Clock readings of a stamped batch gemv launch, per tile (indexed by its
+// place in the tile table): [0] the work-group starts the tile, [1] it is
+// done with it, [2] the tile's problem (high 32 bits) and rows (low 32),
+// [3] ids (high 32 bits: bits 16-19 XCC, bits 0-7 HW_ID[15:8]) and the
+// work-group (low 32).
+constexpr int STAMPS_PER_TILE = 4;
+const void *batch_gemv_stamped_f32(int vec_bytes, int unroll);
+const void *batch_gemv_stamped_bf16(int vec_bytes, int unroll);
 
 const void *batch_kernel_f32(int acc, int vec_bytes, int unroll, bool gemv);
 const void *batch_kernel_bf16(int acc, int vec_bytes, int unroll, bool gemv);

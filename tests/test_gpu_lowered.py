@@ -305,7 +305,7 @@ def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
             lda = A.shape[1]
             ad = pr[2].data_ptr()
             vec = n > 0 and ad % vb == 0 and (lda * eb) % vb == 0 and xd.data_ptr() % min(E * 4, 16) == 0
-            heads = not vec and E > 1 and vb <= 8 and n >= 64 * U * E and E * (-(-n // 4) * 4) <= BATCH_LDS_X
+            heads = not vec and E > 1 and vb <= 8 and n >= 64 * E and E * (-(-n // 4) * 4) <= BATCH_LDS_X
             if heads:
                 # each row from its own start: a head up to its first vector boundary
                 pred = [None] * A.shape[0]
@@ -345,9 +345,11 @@ def test_batch_matches_lowered_expressions_bitwise(gpu_device, storage, kn):
 @pytest.mark.parametrize("storage", ["bf16", "f16", "f32"])
 def test_batch_gemv_row_heads_bitwise(gpu_device, storage):
     """gemv rows that start inside a vector (row pitch not a multiple of the
-    8-byte vector, or x misaligned), long enough for the head form: every
-    head length occurs, and each row matches the row expression of 64 lanes
-    with its own misaligned start, bit for bit."""
+    8-byte vector, or x misaligned), long enough for the head form (from one
+    vector per lane up; row counts that are not a multiple of the 2E rows a
+    pair block spans, and a problem of 3 rows): every head length occurs, and
+    each row matches the row expression of 64 lanes with its own misaligned
+    start, bit for bit."""
     from tests.test_gpu_batch import _dev_copy
 
     kn = dict(block=512, vec_bytes=8, unroll=4, split=262144, wg_per_cu=8)
@@ -356,11 +358,11 @@ def test_batch_gemv_row_heads_bitwise(gpu_device, storage):
     g = W.gen(77)
     cases = []          # (A on the CPU, x, y, device A, device x, device y, alpha, beta)
     for j, (m, n) in enumerate([(37, 64 * U * E + 1), (29, 64 * U * E + 3), (23, 64 * U * E + 5), (19, 2047),
-                                (17, 64 * U * E)]):
+                                (31, 64 * E + 3), (13, 64 * E * 2 + 1), (3, 64 * E + 1), (17, 64 * U * E)]):
         A = W.normal((m, n), g, storage)
         x = W.normal(n, g)
         y = W.normal(m, g)
-        xd = _dev_copy(x, 1 if j == 4 else 0)     # the last: aligned rows, misaligned x
+        xd = _dev_copy(x, 1 if j == 7 else 0)     # the last: aligned rows, misaligned x
         cases.append((A, x, y, A.to(DEV), xd, y.to(DEV), 1.25, 0.5 if j % 2 == 0 else 0.0))
     problems = [("gemv", a, Ad, xd, b, yd) for (_, _, _, Ad, xd, yd, a, b) in cases]
     banner("batch gemv row heads", storage)
@@ -376,7 +378,7 @@ def test_batch_gemv_row_heads_bitwise(gpu_device, storage):
         for r in range(m):
             by_mis.setdefault(((ad + r * n * eb) % vb) // eb, []).append(r)
         if storage != "f32":
-            assert len(by_mis) == E or n % E == 0            # all head lengths occur when the pitch is odd
+            assert len(by_mis) == min(E, m) or n % E == 0    # all head lengths occur when the pitch is odd
         for mis, rows in by_mis.items():
             pred = _gemv_model_rows(A, x, y, alpha, beta, rows, 64, U, vb, eb, misalign_elems=mis)
             bad = [r for r, p in zip(rows, pred) if np.float32(got[r]).view(np.uint32) != np.float32(p).view(np.uint32)]
