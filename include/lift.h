@@ -160,8 +160,9 @@ typedef struct lift_knobs {
                               elements, whole rows) */
     int32_t wg_per_cu;     /* grid size in work-groups per compute unit when
                               split is 0 (per-call forms), the grid cap of
-                              the work-group-per-row gemv, and the size of
-                              the persistent grid (batched form) */
+                              the work-group-per-row gemv, and the cap of
+                              the persistent grid per compute unit (batched
+                              form: never more than fit on a unit at once) */
     int32_t row_split;     /* gemv only: 1 = each wavefront owns rows_per_wave
                               rows; 2 = all threads of a work-group split each
                               row (then rows_per_wave is 1 or 2 and unroll 2,
@@ -421,16 +422,20 @@ lift_status lift_time_next_launch(hipEvent_t start, hipEvent_t stop);
  * its arrival is counted, and at its end (the combining work-group: after
  * the combine), then ids (bit 32: the work-group that combined; bits 16-19:
  * its XCC; bits 0-7: HW_ID[15:8], CU / shader array / shader engine), then
- * one unused word.  If the next call is lift_batch_run instead (binary32
- * accumulation, F32 or BF16 storage), its gemv launch runs the stamped
- * instance of its kernel, which writes 4 words per gemv tile (in the order
- * of the batch's tile table; `capacity` counts tiles): the clock when a
+ * one unused word (a launch of one work-group, which writes the result
+ * itself, takes the store, arrival and end readings together).  If the next call is lift_batch_run instead (binary32
+ * accumulation, F32 or BF16 storage), both of its launches run the stamped
+ * instances of their kernels, which write 4 words per tile (`capacity`
+ * counts tiles): the reduction tiles in the order of that launch's tile
+ * table, then the gemv tiles in theirs.  Per tile: the clock when a
  * work-group takes the tile and when it is done with it, the tile's problem
- * index (high 32 bits) and row count (low 32), and ids (high 32 bits, as
- * above) with the work-group (low 32).  *clock_khz receives the clock's rate.  One-shot; that
- * launch fails with LIFT_EUNSUPPORTED for another storage, accumulation or
- * vector width and LIFT_EINVAL if its grid (tile count) exceeds `capacity`
- * (the hook is cleared either way).  stamps == NULL disarms it.
+ * index (high 32 bits) and length (low 32: rows of a gemv tile; vectors, or
+ * elements where the problem is read element-wise, of a reduction tile),
+ * and ids (high 32 bits, as above) with the work-group (low 32).
+ * *clock_khz receives the clock's rate.  One-shot; that run fails with
+ * LIFT_EUNSUPPORTED for another storage, accumulation or vector width and
+ * LIFT_EINVAL if its tile count exceeds `capacity` (the hook is cleared
+ * either way).  stamps == NULL disarms it.
  * LIFT_EINVAL: capacity <= 0, stamps not 8-byte aligned or clock_khz NULL. */
 lift_status lift_stamp_next_launch(uint64_t *stamps, int64_t capacity, int32_t *clock_khz);
 

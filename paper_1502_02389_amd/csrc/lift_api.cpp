@@ -86,6 +86,28 @@ lift_status max_block(const void *kernel, int *out)
     return LIFT_OK;
 }
 
+// How many work-groups of `block` threads of a kernel fit on one compute
+// unit at once (registers, LDS, wave slots), cached per kernel and size.
+lift_status resident_per_cu(const void *kernel, int block, int *out)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<std::pair<const void *, int>, int>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto &kv : cache)
+        if (kv.first.first == kernel && kv.first.second == block) {
+            *out = kv.second;
+            return LIFT_OK;
+        }
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    n = std::max(n, 1);
+    cache.emplace_back(std::make_pair(kernel, block), n);
+    *out = n;
+    return LIFT_OK;
+}
+
 // Work-items of one dispatch are counted in 32 bits (the dispatch packet's
 // grid size).
 constexpr int64_t MAX_DISPATCH_ITEMS = 0xFFFFFFFFLL;
@@ -927,6 +949,11 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
             sorted[kd][i] = tiles[kd][(size_t)order[i]];
     }
 
+    // Each launch's grid: at most wg_per_cu work-groups per CU, and no more
+    // than fit on one at once.  (A persistent grid larger than what the CUs
+    // hold would park the excess work-groups until resident ones drain the
+    // tile counter; each would then run its first tile, taken by index and
+    // among the largest, at the end of the launch.)
     const void *kern[2] = {batch_table(storage, acc, vb, k.unroll, false),
                            batch_table(storage, acc, vb, k.unroll, true)};
     if (!kern[0] || !kern[1])
@@ -935,6 +962,39 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     st = cu_count(&cus);
     if (st != LIFT_OK)
         return st;
+    int64_t resident[2];
+    for (int kd = 0; kd < 2; ++kd) {
+        int fit = 1;
+        st = resident_per_cu(kern[kd], k.block, &fit);
+        if (st != LIFT_OK)
+            return st;
+        resident[kd] = (int64_t)cus * std::min<int64_t>(k.wg_per_cu, fit);
+    }
+    // The gemv launch's last round of tiles (one per work-group) is cut in
+    // quarters of whole row groups: the launch then ends on short tiles, so
+    // its work-groups finish within a fraction of a tile of one another.
+    // (A gemv row's result does not depend on its tile; the reduction tiles
+    // are the problems' work-group chunks and stay as planned.)
+    {
+        std::vector<BatchTile> &g = sorted[1];
+        const size_t cut = g.size() - (size_t)std::min<int64_t>((int64_t)g.size(), resident[1]);
+        std::vector<std::pair<int64_t, BatchTile>> pieces;
+        for (size_t i = cut; i < g.size(); ++i) {
+            const BatchTile tl = g[i];
+            const int64_t n = hp[tl.problem].n;
+            const int64_t group = 2 * e;   // a row pair, or a heads tile's pairs of every phase
+            const int64_t sub = std::max<int64_t>(group, ((tl.len + 3) / 4 + group - 1) / group * group);
+            for (int64_t r = 0; r < tl.len; r += sub) {
+                BatchTile pc{tl.problem, tl.index, tl.begin + r, std::min(sub, tl.len - r)};
+                pieces.push_back({pc.len * std::max<int64_t>(n, 64 * k.unroll * e) * eb, pc});
+            }
+        }
+        std::stable_sort(pieces.begin(), pieces.end(),
+                         [](const auto &x, const auto &y) { return x.first > y.first; });
+        g.resize(cut);
+        for (const auto &pc : pieces)
+            g.push_back(pc.second);
+    }
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess)
@@ -946,7 +1006,7 @@ lift_status batch_plan(const lift_problem *probs, int32_t count, int storage, in
     auto up = [](int64_t v) { return (v + 255) / 256 * 256; };
     int64_t grid[2], off_ct[2], off_gc[2], off = 0;
     for (int kd = 0; kd < 2; ++kd) {
-        grid[kd] = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * k.wg_per_cu, (int64_t)sorted[kd].size()));
+        grid[kd] = std::max<int64_t>(1, std::min<int64_t>(resident[kd], (int64_t)sorted[kd].size()));
         off_ct[kd] = off;
         off_gc[kd] = off + 256;
         off = off_gc[kd] + up((grid[kd] + ARRIVAL_GROUP - 1) / ARRIVAL_GROUP * WS_GROUP_STRIDE);
@@ -1288,8 +1348,9 @@ lift_status lift_batch_run(lift_batch *b, hipStream_t stream)
     // pair of events fills the other ends when there are two launches).
     const hipEvent_t t0 = g_time_start, t1 = g_time_stop;
     g_time_start = g_time_stop = nullptr;
-    // an armed stamp hook takes the gemv launch's stamped instance (one-shot)
-    const void *gemv_kern = b->kern[1];
+    // an armed stamp hook takes both launches' stamped instances (one-shot)
+    const void *kern[2] = {b->kern[0], b->kern[1]};
+    int64_t grid[2] = {b->grid[0], b->grid[1]};
     uint64_t *stamps = nullptr;
     if (g_stamps) {
         stamps = g_stamps;
@@ -1297,12 +1358,22 @@ lift_status lift_batch_run(lift_batch *b, hipStream_t stream)
         g_stamps = nullptr;
         if (b->acc != LIFT_ACC_F32 || (b->storage != LIFT_F32 && b->storage != LIFT_BF16))
             return LIFT_EUNSUPPORTED;
-        if (b->ntiles[1] > cap)
+        if (b->ntiles[0] + b->ntiles[1] > cap)
             return LIFT_EINVAL;
-        gemv_kern = b->storage == LIFT_F32 ? batch_gemv_stamped_f32(b->vb, b->unroll)
-                                           : batch_gemv_stamped_bf16(b->vb, b->unroll);
-        if (!gemv_kern)
-            return LIFT_EUNSUPPORTED;
+        int cus = 0;
+        lift_status st = cu_count(&cus);
+        if (st != LIFT_OK)
+            return st;
+        for (int kd = 0; kd < 2; ++kd) {
+            kern[kd] = b->storage == LIFT_F32 ? batch_stamped_f32(b->vb, b->unroll, kd == 1)
+                                              : batch_stamped_bf16(b->vb, b->unroll, kd == 1);
+            if (!kern[kd])
+                return LIFT_EUNSUPPORTED;
+            int fit = 1;
+            if ((st = resident_per_cu(kern[kd], b->block, &fit)) != LIFT_OK)
+                return st;
+            grid[kd] = std::min<int64_t>(grid[kd], (int64_t)cus * fit);
+        }
     }
     const int first = b->ntiles[0] > 0 ? 0 : 1, last = b->ntiles[1] > 0 ? 1 : 0;
     for (int kd = first; kd <= last; ++kd) {
@@ -1313,9 +1384,9 @@ lift_status lift_batch_run(lift_batch *b, hipStream_t stream)
             g_time_stop = kd == last ? t1 : b->ev[0];
         }
         BatchArgs a = b->args[kd];
-        if (kd == 1)
-            a.stamps = stamps;
-        lift_status st = launch(kd == 1 ? gemv_kern : b->kern[kd], b->grid[kd], b->block, &a, stream);
+        if (stamps)  // the reduction tiles' words first, then the gemv tiles'
+            a.stamps = stamps + (kd == 1 ? b->ntiles[0] : 0) * STAMPS_PER_TILE;
+        lift_status st = launch(kern[kd], grid[kd], b->block, &a, stream);
         if (st != LIFT_OK) {
             g_time_start = g_time_stop = nullptr;
             return st;

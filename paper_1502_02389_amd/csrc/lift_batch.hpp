@@ -308,7 +308,8 @@ __device__ __forceinline__ void gemv_tile_lx(const BatchProblem &p, const BatchT
     // the plain copy of x serves every row
     for (int64_t r = tl.begin + (threadIdx.x >> 6) * R; r < end; r += waves * R)
         gemv_rows_phase<T, ACC, VB, R, U>(p, r, 1, end, xl, 0, lane);
-    __syncthreads();  // every wave is done with xl before the next tile rewrites it
+    // the caller's draw of the next tile ends with barriers: every wave is
+    // done with xl before the next tile rewrites it
 }
 
 // Rows [begin, begin + len) of a gemv problem with row heads (vec == 2): the
@@ -334,7 +335,34 @@ __device__ __forceinline__ void gemv_tile_skew(const BatchProblem &p, const Batc
         if (r0 < end)   // wave-uniform
             gemv_rows_phase<T, ACC, VB, 2, U>(p, r0, E, end, xl, stride, lane);
     }
-    __syncthreads();  // every wave is done with xl before the next tile rewrites it
+    // the caller's draw of the next tile ends with barriers (as gemv_tile_lx)
+}
+
+// Stamped instances: thread 0 records when its work-group takes a tile and
+// what the tile is, then (after a barrier, every wave done) when it is done.
+template <bool STAMP>
+__device__ __forceinline__ void stamp_tile_start(const BatchArgs &a, int ti, const BatchTile &tl)
+{
+    if constexpr (STAMP) {
+        if (threadIdx.x == 0) {
+            const uint32_t xcc = __builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (3 << 11));  // XCC_ID[3:0]
+            const uint32_t hw = __builtin_amdgcn_s_getreg((4 << 0) | (8 << 6) | (7 << 11));    // HW_ID[15:8]
+            uint64_t *w = a.stamps + (int64_t)ti * STAMPS_PER_TILE;
+            w[0] = (uint64_t)wall_clock64();
+            w[2] = ((uint64_t)(uint32_t)tl.problem << 32) | (uint32_t)tl.len;
+            w[3] = ((uint64_t)((xcc << 16) | hw) << 32) | (uint32_t)blockIdx.x;
+        }
+    }
+}
+
+template <bool STAMP>
+__device__ __forceinline__ void stamp_tile_end(const BatchArgs &a, int ti)
+{
+    if constexpr (STAMP) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            a.stamps[(int64_t)ti * STAMPS_PER_TILE + 1] = (uint64_t)wall_clock64();
+    }
 }
 
 // Next tile for the work-group: thread 0 draws it from the shared counter
@@ -355,12 +383,14 @@ __device__ __forceinline__ int fetch_tile(unsigned *counter, int *s_tile)
 // At most 512 threads per work-group: the widest instance (dot, 16-byte
 // loads, 8 in flight) needs about 160 VGPRs, more than a 1024-thread
 // work-group leaves each wave.
-// The loop is written so that its only back edge passes through fetch_tile:
-// no continue / break, and every branch inside it is on a work-group-uniform
-// scalar.  (A loop whose head is thread 0's conditional fetch, re-entered
-// from several places, can be restructured by the compiler into a back edge
-// that reaches the barrier without the fetch, splitting wave 0 around it.)
-template <class T, int ACC, int VB, int U>
+// The loop is written so that its only back edge passes through the tile's
+// draw of the next one (thread 0's atomic, then a barrier every thread
+// reaches): no continue / break, and every branch inside it is on a
+// work-group-uniform scalar.  (A loop whose head is thread 0's conditional
+// fetch, re-entered from several places, can be restructured by the
+// compiler into a back edge that reaches the barrier without the fetch,
+// splitting wave 0 around it.)
+template <class T, int ACC, int VB, int U, bool STAMP = false>
 __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
 {
     using BT = typename BlockT<ACC>::type;
@@ -376,8 +406,10 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
     int ti = blockIdx.x;  // the grid never exceeds the tile count
     while (ti < a.ntiles) {
         const BatchTile tl = a.tiles[ti];
+        stamp_tile_start<STAMP>(a, ti, tl);
         const BatchProblem p = a.probs[tl.problem];
         const int kind = __builtin_amdgcn_readfirstlane(p.kind);
+        int next;
         const int vec = __builtin_amdgcn_readfirstlane(p.vec);
 
         {
@@ -390,15 +422,21 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
 
             if (t == 0) {
                 store_coherent(a.slots + (p.slot_base + tl.index) * WS_SLOT, to_slot<ACC>(wg));
+                // the next tile is drawn here, its round trip overlapping the
+                // partial's store (the work-group is all but done with this one)
+                const unsigned ticket =
+                    __hip_atomic_fetch_add(&a.counters[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 unsigned prev = __hip_atomic_fetch_add(&a.pcount[tl.problem], 1u, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
                 s_last = prev == (unsigned)(p.ntiles - 1);
+                s_tile = (int)gridDim.x + (int)ticket;
             }
             __syncthreads();
             const int last = __builtin_amdgcn_readfirstlane(s_last);
+            next = __builtin_amdgcn_readfirstlane(s_tile);
             if (last) {
                 ST acc = zero_of<ST>();
                 for (int64_t i = t; i < p.ntiles; i += B)
@@ -410,7 +448,10 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
                 }
             }
         }
-        ti = fetch_tile(&a.counters[0], &s_tile);
+        stamp_tile_end<STAMP>(a, ti);
+        // thread 0 writes s_tile and s_last again only after the next tile's
+        // tree, whose barrier every thread reaches after reading them here
+        ti = next;
     }
 
     // The last work-group out (two-level arrival) resets the counters for the
@@ -437,16 +478,7 @@ __global__ void __launch_bounds__(512) batch_gemv_kernel(BatchArgs a)
     int ti = blockIdx.x;  // the grid never exceeds the tile count
     while (ti < a.ntiles) {
         const BatchTile tl = a.tiles[ti];
-        if constexpr (STAMP) {
-            if (t == 0) {
-                const uint32_t xcc = __builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (3 << 11));   // XCC_ID[3:0]
-                const uint32_t hw = __builtin_amdgcn_s_getreg((4 << 0) | (8 << 6) | (7 << 11));     // HW_ID[15:8]
-                a.stamps[(int64_t)ti * STAMPS_PER_TILE + 0] = (uint64_t)wall_clock64();
-                a.stamps[(int64_t)ti * STAMPS_PER_TILE + 2] = ((uint64_t)(uint32_t)tl.problem << 32) | (uint32_t)tl.len;
-                a.stamps[(int64_t)ti * STAMPS_PER_TILE + 3] =
-                    ((uint64_t)((xcc << 16) | hw) << 32) | (uint32_t)blockIdx.x;
-            }
-        }
+        stamp_tile_start<STAMP>(a, ti, tl);
         const BatchProblem p = a.probs[tl.problem];
         const int vec = __builtin_amdgcn_readfirstlane(p.vec);
         const int in_lds = __builtin_amdgcn_readfirstlane((int)(p.n <= BATCH_LDS_X));
@@ -464,11 +496,7 @@ __global__ void __launch_bounds__(512) batch_gemv_kernel(BatchArgs a)
             else
                 gemv_tile<T, ACC, EB, U>(p, tl);
         }
-        if constexpr (STAMP) {  // every wave is done with the tile (its stores issued)
-            __syncthreads();
-            if (t == 0)
-                a.stamps[(int64_t)ti * STAMPS_PER_TILE + 1] = (uint64_t)wall_clock64();
-        }
+        stamp_tile_end<STAMP>(a, ti);
         ti = fetch_tile(&a.counters[0], &s_tile);
     }
     if (t == 0 && arrive(&a.counters[1], a.groups)) {
@@ -516,26 +544,33 @@ const void *pick_batch(int acc, int vec_bytes, int unroll, bool gemv)
     }
 }
 
-// The stamped gemv-tile instances (binary32 accumulation).
+// The stamped instances (binary32 accumulation) of both kernels.
+template <class T, int VB, int U>
+const void *pick_batch_stamped_kind(bool gemv)
+{
+    return gemv ? reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, U, true>)
+                : reinterpret_cast<const void *>(&batch_kernel<T, ACC_F32, VB, U, true>);
+}
+
 template <class T, int VB>
-const void *pick_batch_gemv_stamped_unroll(int unroll)
+const void *pick_batch_stamped_unroll(int unroll, bool gemv)
 {
     switch (unroll) {
-    case 1: return reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, 1, true>);
-    case 2: return reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, 2, true>);
-    case 4: return reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, 4, true>);
-    case 8: return reinterpret_cast<const void *>(&batch_gemv_kernel<T, ACC_F32, VB, 8, true>);
+    case 1: return pick_batch_stamped_kind<T, VB, 1>(gemv);
+    case 2: return pick_batch_stamped_kind<T, VB, 2>(gemv);
+    case 4: return pick_batch_stamped_kind<T, VB, 4>(gemv);
+    case 8: return pick_batch_stamped_kind<T, VB, 8>(gemv);
     default: return nullptr;
     }
 }
 
 template <class T>
-const void *pick_batch_gemv_stamped(int vec_bytes, int unroll)
+const void *pick_batch_stamped(int vec_bytes, int unroll, bool gemv)
 {
     switch (vec_bytes) {
-    case 4: return pick_batch_gemv_stamped_unroll<T, 4>(unroll);
-    case 8: return pick_batch_gemv_stamped_unroll<T, 8>(unroll);
-    case 16: return pick_batch_gemv_stamped_unroll<T, 16>(unroll);
+    case 4: return pick_batch_stamped_unroll<T, 4>(unroll, gemv);
+    case 8: return pick_batch_stamped_unroll<T, 8>(unroll, gemv);
+    case 16: return pick_batch_stamped_unroll<T, 16>(unroll, gemv);
     default: return nullptr;
     }
 }

@@ -8,9 +8,9 @@ const void *batch_kernel_bf16(int acc, int vec_bytes, int unroll, bool gemv)
     return pick_batch<BF16>(acc, vec_bytes, unroll, gemv);
 }
 
-const void *batch_gemv_stamped_bf16(int vec_bytes, int unroll)
+const void *batch_stamped_bf16(int vec_bytes, int unroll, bool gemv)
 {
-    return pick_batch_gemv_stamped<BF16>(vec_bytes, unroll);
+    return pick_batch_stamped<BF16>(vec_bytes, unroll, gemv);
 }
 
 }  // namespace lift

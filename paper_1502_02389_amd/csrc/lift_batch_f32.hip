@@ -8,9 +8,9 @@ const void *batch_kernel_f32(int acc, int vec_bytes, int unroll, bool gemv)
     return pick_batch<F32>(acc, vec_bytes, unroll, gemv);
 }
 
-const void *batch_gemv_stamped_f32(int vec_bytes, int unroll)
+const void *batch_stamped_f32(int vec_bytes, int unroll, bool gemv)
 {
-    return pick_batch_gemv_stamped<F32>(vec_bytes, unroll);
+    return pick_batch_stamped<F32>(vec_bytes, unroll, gemv);
 }
 
 }  // namespace lift

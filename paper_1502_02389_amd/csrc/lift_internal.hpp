@@ -145,17 +145,18 @@ struct BatchArgs {
     char *slots;
     int64_t ntiles;
     int32_t result_f64;
-    uint64_t *stamps;     // stamped gemv instances only: STAMPS_PER_TILE words per tile
+    uint64_t *stamps;     // stamped instances only: STAMPS_PER_TILE words per tile
 };
 
-// Clock readings of a stamped batch gemv launch, per tile (indexed by its
-// place in the tile table): [0] the work-group starts the tile, [1] it is
-// done with it, [2] the tile's problem (high 32 bits) and rows (low 32),
-// [3] ids (high 32 bits: bits 16-19 XCC, bits 0-7 HW_ID[15:8]) and the
-// work-group (low 32).
+// Clock readings of a stamped batch launch, per tile (indexed by its place
+// in that launch's tile table): [0] the work-group starts the tile, [1] it
+// is done with it, [2] the tile's problem (high 32 bits) and length (low
+// 32: units of a reduction tile -- vectors, or elements where its problem
+// is read element-wise -- rows of a gemv tile), [3] ids (high 32
+// bits: bits 16-19 XCC, bits 0-7 HW_ID[15:8]) and the work-group (low 32).
 constexpr int STAMPS_PER_TILE = 4;
-const void *batch_gemv_stamped_f32(int vec_bytes, int unroll);
-const void *batch_gemv_stamped_bf16(int vec_bytes, int unroll);
+const void *batch_stamped_f32(int vec_bytes, int unroll, bool gemv);
+const void *batch_stamped_bf16(int vec_bytes, int unroll, bool gemv);
 
 const void *batch_kernel_f32(int acc, int vec_bytes, int unroll, bool gemv);
 const void *batch_kernel_bf16(int acc, int vec_bytes, int unroll, bool gemv);

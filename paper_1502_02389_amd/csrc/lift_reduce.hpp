@@ -271,6 +271,26 @@ __device__ __forceinline__ void stamp(const ReduceArgs &a, int k)
     }
 }
 
+// Stamped instances, thread 0 of a work-group whose arrival is counted:
+// the arrival time (also its end, unless it combines), its ids and whether
+// it combines.  A single work-group stamps its partial's store here too.
+template <bool STAMP>
+__device__ __forceinline__ void stamp_arrival(const ReduceArgs &a, int last)
+{
+    if constexpr (STAMP) {
+        __builtin_amdgcn_sched_barrier(0);
+        uint64_t *w = a.stamps + (int64_t)blockIdx.x * STAMPS_PER_WG;
+        const uint64_t now = (uint64_t)wall_clock64();
+        if (gridDim.x == 1)
+            w[3] = now;
+        w[4] = now;
+        w[5] = now;
+        const uint32_t xcc = __builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (3 << 11));  // XCC_ID[3:0]
+        const uint32_t hw = __builtin_amdgcn_s_getreg((4 << 0) | (8 << 6) | (7 << 11));    // HW_ID[15:8]: CU, SH, SE
+        w[6] = ((uint64_t)(unsigned)last << 32) | ((uint64_t)xcc << 16) | hw;
+    }
+}
+
 template <class T, int OP, int ACC, int VB, int U, bool STAMP = false>
 __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
 {
@@ -367,8 +387,10 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     stamp<STAMP>(a, 2);
 
     if (gridDim.x == 1) {
-        if (t == 0)
+        if (t == 0) {
             write_result(a.result, a.result_f64, wg);
+            stamp_arrival<STAMP>(a, 1);  // the only work-group combines: stored, arrived and done at once
+        }
         return;
     }
 
@@ -389,16 +411,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
             __builtin_amdgcn_sched_barrier(0);
         }
         last = arrive(reinterpret_cast<unsigned *>(a.ws), reinterpret_cast<char *>(a.ws) + WS_GROUPS) ? 1 : 0;
-        if constexpr (STAMP) {  // after the arrival's atomics have returned (last depends on them)
-            __builtin_amdgcn_sched_barrier(0);
-            const uint64_t now = (uint64_t)wall_clock64();
-            a.stamps[(int64_t)blockIdx.x * STAMPS_PER_WG + 4] = now;
-            a.stamps[(int64_t)blockIdx.x * STAMPS_PER_WG + 5] = now;
-            const uint32_t xcc = __builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (3 << 11));   // XCC_ID[3:0]
-            const uint32_t hw = __builtin_amdgcn_s_getreg((4 << 0) | (8 << 6) | (7 << 11));     // HW_ID[15:8]: CU, SH, SE
-            a.stamps[(int64_t)blockIdx.x * STAMPS_PER_WG + 6] =
-                ((uint64_t)(unsigned)last << 32) | ((uint64_t)xcc << 16) | hw;
-        }
+        stamp_arrival<STAMP>(a, last);  // after the arrival's atomics have returned (last depends on them)
     }
     last = __builtin_amdgcn_readfirstlane(last);  // lane 0's decision, for the whole wave
     if (!last)

@@ -1,0 +1,104 @@
+"""The diagnostic stamp hook (lift_stamp_next_launch).
+
+A stamped launch runs another instance of the same kernel: its results must
+equal the plain launch's bit for bit, and its clock readings must be well
+formed -- per work-group of a reduction, six readings in the order the
+kernel passes those points and exactly one combining work-group; per tile
+of a batch run, one record for every tile of the plan (the reduction
+launch's tiles first, then the gemv launch's), each taken before it ends,
+naming a problem of the right kind, with every gemv row counted once.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1502_02389_amd as L
+import workloads as W
+from tests.gpu_util import banner
+from tests.test_gpu_batch import build, small_spec
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.mark.parametrize("op", ["asum", "dot"])
+@pytest.mark.parametrize("n", [(1 << 20) + 13, 3000])
+def test_reduce_stamps(gpu_device, op, n):
+    banner("stamps", op, n)
+    g = W.gen(71)
+    x = W.uniform(n, g).to(DEV)
+    y = W.uniform(n, g).to(DEV)
+    kn = L.knobs(block=256, vec_bytes=16, unroll=4)
+
+    def call():
+        return L.asum(x, knobs=kn) if op == "asum" else L.dot(x, y, knobs=kn)
+
+    plain = call().item()
+    cap = L.lift_max_workgroups()
+    buf = torch.zeros((cap, 8), dtype=torch.int64, device=DEV)
+    torch.cuda.synchronize()
+    st, khz = L.lift_stamp_next_launch(buf.data_ptr(), cap)
+    assert st == 0 and khz > 0
+    stamped = call().item()
+    torch.cuda.synchronize()
+    assert np.float32(stamped).view(np.uint32) == np.float32(plain).view(np.uint32)
+
+    b = buf.cpu().numpy()
+    grid = int((b[:, 0] != 0).sum())
+    assert grid >= 1
+    assert not b[grid:].any(), "records beyond the grid"
+    b = b[:grid]
+    clocks = b[:, :6]  # 64-bit clock counts stay far below 2^63
+    assert np.all(clocks > 0)
+    assert np.all(np.diff(clocks, axis=1) >= 0), "readings out of kernel order"
+    combiners = (b[:, 6] >> 32) & 1
+    assert int(combiners.sum()) == 1
+    # the next launch is plain again
+    assert call().item() == plain
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_batch_stamps(gpu_device, storage):
+    banner("batch stamps", storage)
+    spec = small_spec(seed=72, n_red=60, n_gemv=12)
+    n_red = len(spec.red_kind)
+    cpu, problems = build(spec, storage=storage, seed=73)
+    b = L.Batch(problems)
+    gemv_y = [pr[5] for pr in problems if pr[0] == "gemv"]
+    y0 = [v.clone() for v in gemv_y]
+
+    def results():
+        red = [b.results[i].clone() for i in range(n_red)]
+        return [r.cpu() for r in red], [v.cpu() for v in gemv_y]
+
+    b.run()
+    torch.cuda.synchronize()
+    plain = results()
+    for v, v0 in zip(gemv_y, y0):
+        v.copy_(v0)
+    cap = b.tiles
+    buf = torch.zeros((cap, 4), dtype=torch.int64, device=DEV)
+    torch.cuda.synchronize()
+    st, khz = L.lift_stamp_next_launch(buf.data_ptr(), cap)
+    assert st == 0 and khz > 0
+    b.run()
+    torch.cuda.synchronize()
+    stamped = results()
+    for p, s in zip(plain[0], stamped[0]):
+        assert p.view(torch.int32).item() == s.view(torch.int32).item()
+    for p, s in zip(plain[1], stamped[1]):
+        assert torch.equal(p.view(torch.int32), s.view(torch.int32))
+
+    t = buf.cpu().numpy()
+    assert np.all(t[:, 0] != 0) and np.all(t[:, 1] != 0), "a tile without a record"
+    assert np.all(t[:, 1] >= t[:, 0])
+    prob = t[:, 2] >> 32
+    length = t[:, 2] & 0xFFFFFFFF
+    is_gemv = prob >= n_red
+    # reduction tiles first, then gemv tiles
+    k = int((~is_gemv).sum())
+    assert not is_gemv[:k].any() and is_gemv[k:].all()
+    assert set(prob[:k].tolist()) == set(range(n_red))
+    for j, (m, n) in enumerate(spec.gemv_mn):
+        assert int(length[prob == n_red + j].sum()) == m, ("rows of gemv", j)
+    b.close()
