@@ -123,7 +123,7 @@ def grid(op: str, storage: str, quick: bool = False):
     if op == "batch":
         blocks = (256, 512) if quick else (128, 256, 512)
         vecs = (16,) if quick else tuple(v for v in (8, 16) if v >= eb)
-        splits = (1 << 15, 1 << 16, 1 << 17) if quick else (1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
+        splits = (1 << 16, 1 << 17, 1 << 18) if quick else tuple(1 << s for s in range(15, 21))
         for b, v, u, s, w in itertools.product(blocks, vecs, (2, 4, 8), splits, (1, 2, 4, 8)):
             yield dict(block=b, vec_bytes=v, unroll=u, split=s, wg_per_cu=w)
         return
@@ -185,13 +185,15 @@ class BatchOperands:
         self.bytes = None
         self.sets = 1
 
-    def time_us(self, acc, k, reps=5, trials=1):
+    def time_us(self, acc, k, reps=5, trials=1, median=False):
+        import statistics
+
         import torch
 
         b = B.Batch(self.problems, acc=acc, knobs=k)
         self.bytes = b.bytes
         ev = B.HipEvents(2)
-        best = float("inf")
+        ts = []
         try:
             for i in range(reps + 2):
                 if i >= 2:
@@ -199,11 +201,11 @@ class BatchOperands:
                 b.run()
                 torch.cuda.synchronize()
                 if i >= 2:
-                    best = min(best, ev.elapsed_ms(0, 1) * 1e3)
+                    ts.append(ev.elapsed_ms(0, 1) * 1e3)
         finally:
             ev.close()
             b.close()
-        return best
+        return statistics.median(ts) if median else min(ts)
 
 
 class Operands:
@@ -334,6 +336,22 @@ def tune_one(op, storage, acc, elements=None, m=None, n=None, quick=False, log=N
         if log:
             log(f"{op} {storage} {acc} {kn} {us:.2f} us {gbs:.0f} GB/s")
     results.sort(key=lambda r: r[0])
+    if op == "batch":
+        # runs of a batch differ by about 1 % from one to the next, as much as
+        # the leading points do: the best 8 are timed again, interleaved over
+        # three rounds, and ranked by their median
+        top = results[:8]
+        again = {i: [] for i in range(len(top))}
+        for _ in range(3):
+            for i, (_, kn, _, _) in enumerate(top):
+                again[i].append(ops.time_us(accc, B.knobs(**kn), reps=5, median=True))
+        import statistics
+
+        results[:8] = sorted(((statistics.median(again[i]), kn, ops.bytes / (statistics.median(again[i]) * 1e-6) / 1e9, d)
+                              for i, (_, kn, _, d) in enumerate(top)), key=lambda r: r[0])
+        if log:
+            for us, kn, gbs, _ in results[:8]:
+                log(f"{op} {storage} {acc} re-timed {kn} {us:.2f} us {gbs:.0f} GB/s")
     us, kn, gbs, d = results[0]
     best = {"knobs": kn, "us": round(us, 3), "GB_s": round(gbs, 1), "bytes": ops.bytes}
     if d is not None:
