@@ -122,6 +122,24 @@ typedef enum lift_interleave {
                                     of split elements */
 } lift_interleave;
 
+/* How the lanes of a work-group take and combine their share of its chunk
+ * in asum / dot (Section 6.2's choices between reorder-stride and plain
+ * split, and between the iterate tree and reduce-seq; Fig. 9c is the last
+ * form with one lane).  Bit 0: the lane partials are folded in lane order
+ * by one thread instead of the tree; bit 1: lane t reduces the t-th
+ * contiguous run of chunk / block vectors instead of vectors t, t + block,
+ * ....  Forms other than the default take binary32 accumulation (LIFT_ACC_F32)
+ * and F32 or BF16 storage, and the chunk partition (LIFT_INTERLEAVE_STRIDE
+ * is LIFT_EINVAL); the sequential forms also take a block of 1 to 32 lanes
+ * (a power of two), their final combine then folding the work-group partials
+ * over that many lanes. */
+typedef enum lift_lane_form {
+    LIFT_LANES_TREE = 0,        /* reorder-stride lanes, tree (the default) */
+    LIFT_LANES_SEQ = 1,         /* reorder-stride lanes, folded in lane order */
+    LIFT_LANES_RUNS_TREE = 2,   /* contiguous runs, tree */
+    LIFT_LANES_RUNS_SEQ = 3     /* contiguous runs, folded in lane order */
+} lift_lane_form;
+
 /* Launch knobs: the parameters the paper's low-level expressions expose
  * (split factor, work-group size, vector width; Fig. 9 and Section 6.2)
  * plus the rows handled together by one wavefront in gemv.  A zero field
@@ -130,7 +148,7 @@ typedef enum lift_interleave {
  * Calls that take no knobs, or are passed knobs == NULL, run with
  *   1. the environment override LIFT_FORCE_CONFIG="key=value,..." if set
  *      (read once per process; keys block (or wg), vec, unroll, rpw, split,
- *      wgcu, rowsplit, lanes, interleave = stride | chunk | 1 | 2; values
+ *      wgcu, rowsplit, lanes, interleave = stride | chunk | 1 | 2, laneform; values
  *      non-negative integers; an unknown key or malformed value makes every
  *      such call return LIFT_EINVAL), applied as if the caller had passed
  *      those knobs (fields the op does not use are ignored);
@@ -144,6 +162,7 @@ typedef enum lift_interleave {
  * overridden. */
 typedef struct lift_knobs {
     int32_t block;         /* work-group size: 64, 128, 256, 512 or 1024
+                              (1 to 32 too for the sequential lane forms)
                               (batched form: at most 512; gemv lowers it to
                               what the instance's registers allow: with
                               many rows x loads in flight, 512 or 256) */
@@ -175,6 +194,7 @@ typedef struct lift_knobs {
     int32_t lanes_per_item; /* MD only: lanes that share one particle's
                               neighbour list: 1, 2, 4, 8 or 16 */
     int32_t interleave;    /* asum / dot only: a lift_interleave value */
+    int32_t lane_form;     /* asum / dot only: a lift_lane_form value */
 } lift_knobs;
 
 /* ---- plain FP32 forms (Fig. 5) --------------------------------------- */

@@ -61,6 +61,10 @@ class Shape:
     step: int = 0    # B * unroll vectors: with interleave, work-group b takes
     interleave: bool = False   # steps b, b + G, ... instead of one chunk
     final_lanes: int = 64      # lanes of the final combine of the G partials
+    runs: bool = False         # lane t takes the t-th contiguous run of C / B
+    #                            vectors (split) instead of t, t + B, ... (reorder-stride)
+    seq: bool = False          # the lane partials meet in one reduce-seq in lane
+    #                            order instead of the tree
 
     @property
     def tail(self) -> int:
@@ -69,7 +73,7 @@ class Shape:
 
 def launch_shape(n: int, elem_bytes: int, vec_bytes: int, block: int, unroll: int, split: int,
                  misalign_elems: int = 0, max_workgroups: int = 8192, interleave: bool = False,
-                 final_lanes: int = 64) -> Shape:
+                 final_lanes: int = 64, lane_form: int = 0) -> Shape:
     """The documented launch rules for an explicit split (elements per chunk).
 
     ``misalign_elems``: how many elements past a vec_bytes boundary x starts.
@@ -77,8 +81,13 @@ def launch_shape(n: int, elem_bytes: int, vec_bytes: int, block: int, unroll: in
     of block * unroll vectors round-robin instead of one chunk each.
     ``final_lanes``: lanes that fold the work-group partials at the end (one
     wavefront in the per-call kernels; a whole work-group in the batched
-    form's per-problem combine).
+    form's per-problem combine); a block of fewer than 64 lanes folds them
+    over its own lanes.
+    ``lane_form``: bit 0 = the lanes meet in lane order, bit 1 = lanes on
+    contiguous runs (the interface's lane forms).
     """
+    if block < 64:
+        final_lanes = min(final_lanes, block)
     e = vec_bytes // elem_bytes
     head = 0 if misalign_elems % e == 0 else e - misalign_elems % e
     head = min(head, n)
@@ -89,7 +98,8 @@ def launch_shape(n: int, elem_bytes: int, vec_bytes: int, block: int, unroll: in
     if -(-nvec // chunk) > max_workgroups:
         chunk = -(-(-(-nvec // max_workgroups)) // step) * step
     grid = max(1, -(-nvec // chunk))
-    return Shape(n, head, e, nvec, block, chunk, grid, step, interleave, final_lanes)
+    return Shape(n, head, e, nvec, block, chunk, grid, step, interleave, final_lanes,
+                 bool(lane_form & 2), bool(lane_form & 1))
 
 
 def _pairwise(values, add):
@@ -108,8 +118,9 @@ def _pairwise(values, add):
 
 
 def _block_tree(lane_values, add):
-    """Wave butterflies (iterate-6 over 64 lanes) then a fold of the wave totals."""
-    waves = P.split(64)(lane_values)
+    """Wave butterflies (iterate-6 over 64 lanes) then a fold of the wave
+    totals; fewer than 64 lanes (a power of two) meet in one pairwise tree."""
+    waves = P.split(64)(lane_values) if len(lane_values) >= 64 else [lane_values]
     totals = [_pairwise(w, add) for w in waves]
     acc = totals[0]
     for t in totals[1:]:
@@ -183,16 +194,25 @@ def _launch(vectors, zero_item, head, tail0, s: Shape, lane_step, scalar_step, a
 
     partials = []
     for b, chunk in enumerate(chunks):                              # map-workgroup
-        lanes = P.split(len(chunk) // B)(P.reorder_stride(B)(chunk))  # lane t: t, t+B, ...
+        if s.runs:
+            lanes = P.split(len(chunk) // B)(chunk)                 # lane t: the t-th run
+        else:
+            lanes = P.split(len(chunk) // B)(P.reorder_stride(B)(chunk))  # lane t: t, t+B, ...
         lane_acc = [list(lane_fold(v)[0]) for v in lanes]           # map-local(reduce-seq)
         if b == 0:
-            for t, h in enumerate(head):                            # scalar head
-                lane_acc[t][0] = scalar_step(lane_acc[t][0], h)
+            for t, h in enumerate(head):                            # scalar head: lane t mod B
+                lane_acc[t % B][0] = scalar_step(lane_acc[t % B][0], h)
         if b == G - 1:
-            for t, v in enumerate(tail0):                           # scalar tail
-                lane_acc[t][0] = scalar_step(lane_acc[t][0], v)
+            for t, v in enumerate(tail0):                           # scalar tail: lane t mod B
+                lane_acc[t % B][0] = scalar_step(lane_acc[t % B][0], v)
         lane_vals = [_pairwise(acc, add) for acc in lane_acc]      # iterate-log2(E)
-        partials.append(_block_tree(lane_vals, add))                # toLocal tree
+        if s.seq:
+            acc = lane_vals[0]                                      # reduce-seq over the lanes
+            for v in lane_vals[1:]:
+                acc = add(acc, v)
+            partials.append(acc)
+        else:
+            partials.append(_block_tree(lane_vals, add))            # toLocal tree
     if G == 1:
         return partials[0]
     # final reduce-seq o join over the work-group partials, by F lanes (one
@@ -213,14 +233,16 @@ def render(shape: Shape) -> str:
     """The expression in the paper's notation (cf. Fig. 9)."""
     s = shape
     lanes_per_chunk = s.chunk // s.block
-    waves = s.block // 64
+    waves = max(1, s.block // 64)
     e_log = int(math.log2(s.e))
+    combine = ("reduce-seq(plus, 0)" if s.seq else
+               "reduce-seq(plus, 0) o map-wave(iterate-6(join o map-local(reduce-seq(plus, 0)) o split-2))"
+               " o split-64")
     wg = (f"join o toGlobal(map-local(map-seq(id))) o split-1\n"
-          f"      o reduce-seq(plus, 0) o map-wave(iterate-6(join o map-local(reduce-seq(plus, 0)) o split-2))"
-          f" o split-64\n"
+          f"      o {combine}\n"
           f"      o join o toLocal(map-local(iterate-{e_log}(join o map(reduce-seq(plus, 0)) o split-2)"
           f" o asScalar o reduce-seq(vect-{s.e}(absAndPlus), vect-{s.e}(0))))\n"
-          f"      o split-{lanes_per_chunk} o reorder-stride-{s.block}")
+          f"      o split-{lanes_per_chunk}" + ("" if s.runs else f" o reorder-stride-{s.block}"))
     text = (f"reduce-seq o join o map-workgroup(\n      {wg}\n    ) o split-{s.chunk} o asVector-{s.e}"
             f"   [{s.grid} work-groups x {waves} waves; head {s.head}, tail {s.tail} scalars]")
     return text

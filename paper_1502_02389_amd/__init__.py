@@ -9,6 +9,7 @@ from .lift import (  # noqa: F401
     ACC, LIFT_ACC_F32, LIFT_ACC_F32_COMP, LIFT_ACC_F32_F64COMBINE, LIFT_BF16, LIFT_EHIP,
     LIFT_EINVAL, LIFT_EUNSUPPORTED, LIFT_EWORKSPACE, LIFT_F16, LIFT_F32, LIFT_F64, LIFT_OK,
     LIFT_INTERLEAVE_CHUNK, LIFT_INTERLEAVE_DEFAULT, LIFT_INTERLEAVE_STRIDE,
+    LIFT_LANES_TREE, LIFT_LANES_SEQ, LIFT_LANES_RUNS_TREE, LIFT_LANES_RUNS_SEQ,
     LiftError, asum, dot, gemv, knobs, library, lift_asum, lift_asum_ex, lift_dot, lift_dot_ex,
     lift_gemv, lift_gemv_ex, lift_knobs, lift_last_hip_error, lift_max_workgroups, lift_scal,
     lift_scal_ex, lift_status_string, lift_time_next_launch, lift_version, lift_workspace_bytes, scal,

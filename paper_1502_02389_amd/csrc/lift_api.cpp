@@ -165,16 +165,23 @@ struct Knobs {
     int row_split;  // 1: wavefront per row group, 2: work-group per row
     int lanes;      // MD: lanes per particle
     int interleave; // reductions: 1 = grid-stride steps, 0 = contiguous chunks
+    int lane_form;  // reductions: a lift_lane_form value
 };
 
 // Checks the caller's knobs (0 = default) and merges them with defaults.
-lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out)
+// `lanes`: the op takes lane forms (asum / dot), whose sequential forms
+// allow work-groups of 1 to 32 lanes.
+lift_status resolve(const lift_knobs *k, Knobs def, int ebytes, Knobs *out, bool lanes = false)
 {
     *out = def;
     if (!k)
         return LIFT_OK;
+    if (k->lane_form < LIFT_LANES_TREE || k->lane_form > LIFT_LANES_RUNS_SEQ)
+        return LIFT_EINVAL;
+    if (lanes)
+        out->lane_form = k->lane_form;
     if (k->block) {
-        if (!pow2_in(k->block, 64, 1024))
+        if (!pow2_in(k->block, lanes && (k->lane_form & LIFT_LANES_SEQ) ? 1 : 64, 1024))
             return LIFT_EINVAL;
         out->block = k->block;
     }
@@ -274,7 +281,7 @@ const TunedEntry *tuned_entry(const char *arch, int cus, int op, int storage, in
 }
 
 // LIFT_FORCE_CONFIG="key=value,...": keys block (or wg), vec, unroll, rpw,
-// split, wgcu, rowsplit, lanes, interleave (stride | chunk); values are
+// split, wgcu, rowsplit, lanes, interleave (stride | chunk), laneform; values are
 // non-negative integers.  Parsed once; a malformed string makes every call
 // without knobs fail with LIFT_EINVAL.
 struct Forced {
@@ -320,6 +327,8 @@ bool parse_forced(const char *text, lift_knobs *k)
             k->lanes_per_item = (int32_t)x;
         else if (key == "interleave")
             k->interleave = (int32_t)x;
+        else if (key == "laneform")
+            k->lane_form = (int32_t)x;
         else
             return false;
         if (x > INT32_MAX && key != "split")
@@ -514,9 +523,17 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
         def.unroll = 4;  // two streams: grid-stride steps of 4 loads of each in flight
         def.interleave = 1;
     }
-    st = resolve(knobs, def, eb, &k);
+    st = resolve(knobs, def, eb, &k, true);
     if (st != LIFT_OK)
         return st;
+    if (k.lane_form) {
+        // the other lane forms: binary32 accumulation, the chunk partition
+        if (acc != LIFT_ACC_F32 || (xt != LIFT_F32 && xt != LIFT_BF16))
+            return LIFT_EUNSUPPORTED;
+        if (knobs->interleave == LIFT_INTERLEAVE_STRIDE)
+            return LIFT_EINVAL;
+        k.interleave = 0;
+    }
 
     // Vector width: the requested one if x (and y) share its alignment
     // phase, else the element size (scalar loads).
@@ -526,7 +543,9 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
         vb = eb;
         split3(x, nullptr, n, eb, vb, &sp);
     }
-    const void *kern = reduce_table(xt, op, acc, vb, k.unroll);
+    const void *kern = !k.lane_form ? reduce_table(xt, op, acc, vb, k.unroll)
+                       : xt == LIFT_F32 ? reduce_lanes_kernel_f32(op, vb, k.unroll, k.lane_form)
+                                        : reduce_lanes_kernel_bf16(op, vb, k.unroll, k.lane_form);
     if (!kern)
         return LIFT_EUNSUPPORTED;
     int cus = 0;
@@ -553,7 +572,7 @@ lift_status reduce_common(int op, int64_t n, int xt, const void *x, const void *
         uint64_t *buf = g_stamps;
         const int64_t cap = g_stamp_capacity;
         g_stamps = nullptr;
-        if (xt != LIFT_F32 || acc != LIFT_ACC_F32 || vb != 16)
+        if (xt != LIFT_F32 || acc != LIFT_ACC_F32 || vb != 16 || k.lane_form)
             return LIFT_EUNSUPPORTED;
         if (grid > cap)
             return LIFT_EINVAL;
@@ -1164,7 +1183,7 @@ lift_status lift_dot_ex_noalloc(int64_t n, lift_dtype xt, const void *x, const v
     if (st != LIFT_OK)
         return st;
     Knobs checked;  // explicit knobs and the override are checked before the first HIP call
-    if (knobs && (st = resolve(knobs, DEF_REDUCE, elem_bytes(xt), &checked)) != LIFT_OK)
+    if (knobs && (st = resolve(knobs, DEF_REDUCE, elem_bytes(xt), &checked, true)) != LIFT_OK)
         return st;
     if (!knobs && forced_config().present && !forced_config().valid)
         return LIFT_EINVAL;

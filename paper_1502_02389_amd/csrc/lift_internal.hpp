@@ -50,6 +50,10 @@ struct ReduceArgs {
 // (CU, shader array, shader engine); [7] unused.
 constexpr int STAMPS_PER_WG = 8;
 const void *reduce_kernel_stamped_f32(int op, int unroll);
+// The other lane forms (lift_lane_form 1-3) of asum / dot, binary32
+// accumulation, chunk partition.
+const void *reduce_lanes_kernel_f32(int op, int vec_bytes, int unroll, int form);
+const void *reduce_lanes_kernel_bf16(int op, int vec_bytes, int unroll, int form);
 
 // map(mult(alpha), x) with the same head / vector / tail split.
 struct ScalArgs {

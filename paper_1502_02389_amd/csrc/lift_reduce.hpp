@@ -291,13 +291,80 @@ __device__ __forceinline__ void stamp_arrival(const ReduceArgs &a, int last)
     }
 }
 
+// The work-group's partial wg (valid in thread 0; every thread calls this
+// after the work-group tree) goes to the combine: with one work-group it is
+// the result; else it is stored to its slot and counted in, and in the
+// work-group that arrives last one wavefront folds all partials -- lane t
+// folds partials t, t + 64, t + 128, ... in that order (COMBINE_LOADS loads
+// in flight), then the wave butterfly -- and writes the result.  No barrier
+// on this path.
+template <int ACC, bool STAMP>
+__device__ __forceinline__ void combine_partials(const ReduceArgs &a, typename BlockT<ACC>::type wg)
+{
+    using ST = typename SlotT<ACC>::type;
+    const int t = threadIdx.x;
+    if (gridDim.x == 1) {
+        if (t == 0) {
+            write_result(a.result, a.result_f64, wg);
+            stamp_arrival<STAMP>(a, 1);  // the only work-group combines: stored, arrived and done at once
+        }
+        return;
+    }
+
+    // The rest is wave 0's: the other waves are done once the tree has their
+    // values (block_sum ends with a barrier).
+    if (t >= 64)
+        return;
+    char *slots = reinterpret_cast<char *>(a.ws) + WS_HEADER;  // 16-byte slots
+    int last = 0;
+    if (t == 0) {
+        store_coherent(slots + (int64_t)blockIdx.x * WS_SLOT, to_slot<ACC>(wg));
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if constexpr (STAMP) {
+            __builtin_amdgcn_sched_barrier(0);
+            stamp<STAMP>(a, 3);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        last = arrive(reinterpret_cast<unsigned *>(a.ws), reinterpret_cast<char *>(a.ws) + WS_GROUPS) ? 1 : 0;
+        stamp_arrival<STAMP>(a, last);  // after the arrival's atomics have returned (last depends on them)
+    }
+    last = __builtin_amdgcn_readfirstlane(last);  // lane 0's decision, for the whole wave
+    if (!last)
+        return;
+
+    // the final reduce-seq o join, by this wavefront
+    constexpr int COMBINE_LOADS = 8;
+    const int64_t G = gridDim.x;
+    ST v = zero_of<ST>();
+    for (int64_t base = 0; base < G; base += 64 * COMBINE_LOADS) {
+        ST p[COMBINE_LOADS];
+#pragma unroll
+        for (int k = 0; k < COMBINE_LOADS; ++k)
+            p[k] = load_coherent<ST>(slots + min(base + t + 64 * k, G - 1) * WS_SLOT);
+#pragma unroll
+        for (int k = 0; k < COMBINE_LOADS; ++k)
+            if (base + t + 64 * k < G)
+                v = merge(v, p[k]);
+    }
+    v = wave_sum(v);
+    if (t == 0) {
+        write_result(a.result, a.result_f64, v);
+        __hip_atomic_store(reinterpret_cast<unsigned *>(a.ws), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if constexpr (STAMP) {
+        __builtin_amdgcn_sched_barrier(0);
+        stamp<STAMP>(a, 5);
+    }
+}
+
 template <class T, int OP, int ACC, int VB, int U, bool STAMP = false>
 __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
 {
     constexpr int E = Elems<T, VB>::value;
     using V = typename Vec<VB>::type;
     using BT = typename BlockT<ACC>::type;
-    using ST = typename SlotT<ACC>::type;
     __shared__ BT lds_block[16];
 
     stamp<STAMP>(a, 0);
@@ -385,63 +452,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a)
     }
     BT wg = block_sum<BT>(acc.value(), lds_block);
     stamp<STAMP>(a, 2);
-
-    if (gridDim.x == 1) {
-        if (t == 0) {
-            write_result(a.result, a.result_f64, wg);
-            stamp_arrival<STAMP>(a, 1);  // the only work-group combines: stored, arrived and done at once
-        }
-        return;
-    }
-
-    // The rest is wave 0's: the other waves are done once the tree has their
-    // values (block_sum ends with a barrier).
-    if (t >= 64)
-        return;
-    char *slots = reinterpret_cast<char *>(a.ws) + WS_HEADER;  // 16-byte slots
-    int last = 0;
-    if (t == 0) {
-        store_coherent(slots + (int64_t)blockIdx.x * WS_SLOT, to_slot<ACC>(wg));
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if constexpr (STAMP) {
-            __builtin_amdgcn_sched_barrier(0);
-            stamp<STAMP>(a, 3);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        last = arrive(reinterpret_cast<unsigned *>(a.ws), reinterpret_cast<char *>(a.ws) + WS_GROUPS) ? 1 : 0;
-        stamp_arrival<STAMP>(a, last);  // after the arrival's atomics have returned (last depends on them)
-    }
-    last = __builtin_amdgcn_readfirstlane(last);  // lane 0's decision, for the whole wave
-    if (!last)
-        return;
-
-    // The final reduce-seq o join, by one wavefront: lane t folds partials
-    // t, t + 64, t + 128, ... in that order (COMBINE_LOADS loads in flight),
-    // then the wave butterfly; no barrier on this path.
-    constexpr int COMBINE_LOADS = 8;
-    const int64_t G = gridDim.x;
-    ST v = zero_of<ST>();
-    for (int64_t base = 0; base < G; base += 64 * COMBINE_LOADS) {
-        ST p[COMBINE_LOADS];
-#pragma unroll
-        for (int k = 0; k < COMBINE_LOADS; ++k)
-            p[k] = load_coherent<ST>(slots + min(base + t + 64 * k, G - 1) * WS_SLOT);
-#pragma unroll
-        for (int k = 0; k < COMBINE_LOADS; ++k)
-            if (base + t + 64 * k < G)
-                v = merge(v, p[k]);
-    }
-    v = wave_sum(v);
-    if (t == 0) {
-        write_result(a.result, a.result_f64, v);
-        __hip_atomic_store(reinterpret_cast<unsigned *>(a.ws), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if constexpr (STAMP) {
-        __builtin_amdgcn_sched_barrier(0);
-        stamp<STAMP>(a, 5);
-    }
+    combine_partials<ACC, STAMP>(a, wg);
 }
 
 // Table of instantiated reduce kernels for storage T.

@@ -25,6 +25,7 @@ LIFT_OK, LIFT_EINVAL, LIFT_EWORKSPACE, LIFT_EHIP, LIFT_EUNSUPPORTED = 0, -1, -2,
 LIFT_F32, LIFT_BF16, LIFT_F16, LIFT_F64 = 0, 1, 2, 3
 LIFT_ACC_F32, LIFT_ACC_F32_COMP, LIFT_ACC_F32_F64COMBINE = 0, 1, 2
 LIFT_INTERLEAVE_DEFAULT, LIFT_INTERLEAVE_STRIDE, LIFT_INTERLEAVE_CHUNK = 0, 1, 2
+LIFT_LANES_TREE, LIFT_LANES_SEQ, LIFT_LANES_RUNS_TREE, LIFT_LANES_RUNS_SEQ = 0, 1, 2, 3
 
 ACC = {"f32": LIFT_ACC_F32, "comp": LIFT_ACC_F32_COMP, "f64combine": LIFT_ACC_F32_F64COMBINE}
 
@@ -50,16 +51,18 @@ class lift_knobs(ctypes.Structure):
         ("row_split", ctypes.c_int32),
         ("lanes_per_item", ctypes.c_int32),
         ("interleave", ctypes.c_int32),
+        ("lane_form", ctypes.c_int32),
     ]
 
 
 def knobs(block=0, vec_bytes=0, unroll=0, rows_per_wave=0, split=0, wg_per_cu=0, row_split=0, lanes_per_item=0,
-          interleave=0):
+          interleave=0, lane_form=0):
     """A lift_knobs struct; every field 0 selects the library's default for it
-    (interleave: LIFT_INTERLEAVE_STRIDE / LIFT_INTERLEAVE_CHUNK, 0 = default).
+    (interleave: LIFT_INTERLEAVE_STRIDE / LIFT_INTERLEAVE_CHUNK, 0 = default;
+    lane_form: a LIFT_LANES_* value, 0 = reorder-stride lanes and a tree).
     Field meanings and allowed values are those of lift_knobs in lift.h."""
     return lift_knobs(block, vec_bytes, unroll, rows_per_wave, split, wg_per_cu, row_split, lanes_per_item,
-                      interleave)
+                      interleave, lane_form)
 
 
 LIFT_KIND_ASUM, LIFT_KIND_DOT, LIFT_KIND_GEMV = 0, 1, 2

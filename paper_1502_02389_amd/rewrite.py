@@ -698,23 +698,34 @@ def derive_reduction(op: str, n: int, **space) -> list:
 # ---------------------------------------------------------------- kernels
 
 
+LANES_SEQ, LANES_RUNS = 1, 2      # lift_lane_form bits (include/lift.h)
+
+
 def kernel_knobs(d: Derivation, elem_bytes: int = 4) -> Optional[dict]:
     """Launch knobs of the streaming reduction kernel that executes the
-    partition of this derivation, or None when the kernel does not implement
-    the expression (lanes on contiguous runs, a sequential combine of the
-    lanes, fewer than 64 lanes per work-group, vectors wider than 16 bytes).
+    partition of this derivation, or None when no kernel implements the
+    expression (more than 1024 lanes, vectors wider than 16 bytes, a tree
+    over fewer than 64 lanes, the other lane forms with work-groups dealt
+    steps round-robin).
 
     The kernel's work-group b takes vectors [b C/E, (b+1) C/E); its lane t
-    folds vectors t, t + B, ... of the chunk (reorder-stride-B) and the B lane
-    partials meet in a tree -- the expression's partition.
+    folds vectors t, t + B, ... of the chunk (reorder-stride-B), or with the
+    lane form's RUNS bit the t-th run of C/(E B) vectors (a plain split), and
+    the B lane partials meet in a tree, or with its SEQ bit in one reduce-seq
+    in lane order -- the expression's partition.
     """
     c = _choice_of(d)
-    if c is None or not c.reorder or not c.tree or c.lanes < 64 or c.lanes > 1024:
+    if c is None or c.lanes > 1024 or (c.tree and c.lanes < 64):
+        return None
+    form = (0 if c.tree else LANES_SEQ) | (0 if c.reorder else LANES_RUNS)
+    if form and c.interleave:
         return None
     vb = c.width * elem_bytes
     if vb > 16 or vb < min(4, elem_bytes):
         return None
     k = {"block": c.lanes, "vec_bytes": vb, "split": c.chunk, "interleave": INTERLEAVE_CHUNK}
+    if form:
+        k["lane_form"] = form
     if c.interleave:                                 # the dealt step is block x unroll
         k.update(interleave=INTERLEAVE_STRIDE, unroll=c.interleave // c.lanes)
     return k

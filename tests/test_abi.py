@@ -56,16 +56,18 @@ def test_enum_values_match_header():
     for name, value in [("LIFT_OK", 0), ("LIFT_EINVAL", -1), ("LIFT_EWORKSPACE", -2), ("LIFT_EHIP", -3),
                         ("LIFT_EUNSUPPORTED", -4), ("LIFT_F32", 0), ("LIFT_BF16", 1), ("LIFT_F16", 2),
                         ("LIFT_F64", 3), ("LIFT_ACC_F32", 0), ("LIFT_ACC_F32_COMP", 1),
-                        ("LIFT_ACC_F32_F64COMBINE", 2)]:
+                        ("LIFT_ACC_F32_F64COMBINE", 2), ("LIFT_LANES_TREE", 0), ("LIFT_LANES_SEQ", 1),
+                        ("LIFT_LANES_RUNS_TREE", 2), ("LIFT_LANES_RUNS_SEQ", 3)]:
         assert re.search(rf"\b{name}\s*=\s*{value}\b", HEADER), name
         assert getattr(B, name) == value
 
 
 def test_struct_layouts():
-    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, row_split, lanes_per_item, interleave
-    assert ctypes.sizeof(B.lift_knobs) == 40
+    # lift_knobs: int32 x4, int64 split, int32 wg_per_cu, row_split, lanes_per_item, interleave,
+    # lane_form (padded to 48)
+    assert ctypes.sizeof(B.lift_knobs) == 48
     assert B.lift_knobs.split.offset == 16 and B.lift_knobs.wg_per_cu.offset == 24
-    assert B.lift_knobs.lanes_per_item.offset == 32
+    assert B.lift_knobs.lanes_per_item.offset == 32 and B.lift_knobs.lane_form.offset == 40
     # lift_problem: int32 kind, int32 reserved, int64 m, n, lda, 3 pointers, 2 floats
     assert ctypes.sizeof(B.lift_problem) == 64
     assert B.lift_problem.a.offset == 32 and B.lift_problem.alpha.offset == 56
@@ -195,6 +197,16 @@ def test_ex_rejects_bad_enums_and_knobs():
         assert L.lift_md_ex(8, X, 4, Y, 2.5, 1.0, 1.0, R, bad) == L.LIFT_EINVAL
     for bad in (B.knobs(interleave=3), B.knobs(interleave=-1)):
         assert L.lift_asum_ex(8, 0, X, 0, 0, R, WS, w, bad) == L.LIFT_EINVAL
+    # lane forms: a value outside the enum (any op), a tree form with fewer
+    # than 64 lanes, a sequential form with a block that is no power of two,
+    # the stride partition; other accumulations and storages are unsupported
+    for bad in (B.knobs(lane_form=4), B.knobs(lane_form=-1), B.knobs(lane_form=2, block=32),
+                B.knobs(lane_form=3, block=24), B.knobs(lane_form=1, interleave=L.LIFT_INTERLEAVE_STRIDE)):
+        assert L.lift_asum_ex(8, 0, X, 0, 0, R, WS, w, bad) == L.LIFT_EINVAL
+    assert L.lift_scal_ex(8, 1.0, X, Y, B.knobs(lane_form=5)) == L.LIFT_EINVAL
+    assert L.lift_scal_ex(8, 1.0, X, Y, B.knobs(lane_form=1, block=8)) == L.LIFT_EINVAL   # no small blocks
+    assert L.lift_asum_ex(8, 0, X, L.LIFT_ACC_F32_COMP, 0, R, WS, w, B.knobs(lane_form=1)) == L.LIFT_EUNSUPPORTED
+    assert L.lift_asum_ex(8, L.LIFT_F16, X, 0, 0, R, WS, w, B.knobs(lane_form=3)) == L.LIFT_EUNSUPPORTED
 
 
 @cpu_only

@@ -110,6 +110,58 @@ def test_dot_matches_lowered_expression_bitwise(gpu_device, case):
     assert abs(got - r) <= 1e-5 * mass
 
 
+# lane forms: form, n, x offset, y offset (elements), storage, block, vec_bytes, unroll, split
+LANE_CASES = [
+    (1, 70_001, 0, 0, "f32", 256, 16, 4, 1 << 15),
+    (1, 30_011, 3, 3, "bf16", 16, 8, 2, 1 << 11),
+    (2, 70_001, 1, 1, "f32", 256, 16, 2, 1 << 15),
+    (2, 100_000, 0, 0, "bf16", 64, 8, 8, 1 << 13),
+    (3, 70_001, 2, 2, "f32", 128, 8, 4, 1 << 13),
+    (3, 20_003, 0, 0, "f32", 1, 16, 1, 1 << 12),            # one lane per work-group (Fig. 9c's shape)
+    (3, 30_001, 1, 1, "bf16", 4, 2, 8, 1 << 10),
+    (3, 40_000, 0, 1, "f32", 32, 16, 2, 1 << 12),           # phases differ: element loads
+]
+
+
+@pytest.mark.parametrize("case", LANE_CASES, ids=[f"form{c[0]}-{c[4]}-n{c[1]}-o{c[2]}.{c[3]}-b{c[5]}-v{c[6]}-u{c[7]}"
+                                                  for c in LANE_CASES])
+def test_lane_forms_match_lowered_expressions_bitwise(gpu_device, case):
+    """asum and dot in the other lane forms (reorder-stride lanes folded in
+    lane order, contiguous runs under the tree or folded in lane order, down
+    to one lane per work-group): every result bit for bit against the
+    expression of that form, and within the plain bars of the oracle."""
+    from tests import binary32 as F32B
+
+    form, n, ox, oy, storage, block, vb, unroll, split = case
+    g = W.gen(950 + form + n % 1000)
+    x = W.uniform(n, g, storage)
+    y = W.uniform(n, g, storage)
+    bx = torch.empty(n + ox, dtype=x.dtype, device=DEV)
+    by = torch.empty(n + oy, dtype=y.dtype, device=DEV)
+    xd, yd = bx[ox:], by[oy:]
+    xd.copy_(x.to(DEV))
+    yd.copy_(y.to(DEV))
+    banner("lowered lane form", case)
+    k = L.knobs(block=block, vec_bytes=vb, unroll=unroll, split=split, lane_form=form)
+    eb = EB[storage]
+    xs = [float(v) for v in x.float().numpy()]
+    ys = [float(v) for v in y.float().numpy()]
+    got = L.asum(xd, knobs=k).item()
+    shape = LW.launch_shape(n, eb, vb, block, unroll, split, misalign_elems=(ox * eb % vb) // eb, lane_form=form)
+    pred = LW.evaluate([np.float32(v) for v in xs], shape, **F32)
+    assert np.float32(got).view(np.uint32) == np.float32(pred).view(np.uint32), ("asum", got, float(pred))
+    assert rel(got, o_asum(x)) <= 1e-5
+    got = L.dot(xd, yd, knobs=k).item()
+    same_phase = (ox * eb) % vb == (oy * eb) % vb
+    vbytes = vb if same_phase else eb
+    shape = LW.launch_shape(n, eb, vbytes, block, unroll, split,
+                            misalign_elems=(ox * eb % vb) // eb if same_phase else 0, lane_form=form)
+    pred = LW.evaluate_dot(xs, ys, shape, add=F32B.add, fma=F32B.fma, zero=0.0)
+    assert np.float32(got).view(np.uint32) == np.float32(pred).view(np.uint32), ("dot", got, pred)
+    r, mass = o_dot(x, y)
+    assert abs(got - r) <= 1e-5 * mass
+
+
 _STEP = {}
 
 

@@ -62,3 +62,26 @@ def test_derived_scal_and_gemv_points(gpu_device):
             yd = y.to(DEV)
             L.gemv(1.0, Ad, xvd, 0.5, yd, knobs=L.knobs(**kn))
             assert np.array_equal(yd.cpu().numpy().astype(np.float64), r), (kn, str(d.expr))
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_every_lane_form_derivation_runs_integer_exact(gpu_device, storage):
+    """Every derived asum / dot expression in the other lane forms (lanes on
+    contiguous runs, lanes folded in order, one lane per work-group) at
+    n = 2^16: its launch gives the exact sum on integer inputs."""
+    n = 1 << 16
+    g = W.gen(83)
+    x = W.integers(n, -8, 8, g, storage)
+    y = W.integers(n, -4, 4, g, storage)
+    ra, rd = o_asum(x), o_dot(x, y)[0]
+    xd, yd = x.to(DEV), y.to(DEV)
+    eb = 4 if storage == "f32" else 2
+    for op in ("asum", "dot"):
+        pts = [(kn, d) for kn, d in R.derived_knob_points(op, n, elem_bytes=eb) if kn.get("lane_form")]
+        assert len(pts) > 50 and {kn["lane_form"] for kn, _ in pts} == {1, 2, 3}
+        assert any(kn["block"] == 1 for kn, _ in pts)
+        banner("derived lane forms", storage, op, len(pts))
+        for kn, d in pts:
+            k = L.knobs(**kn)
+            got = L.asum(xd, knobs=k).item() if op == "asum" else L.dot(xd, yd, knobs=k).item()
+            assert got == (ra if op == "asum" else rd), (kn, str(d.expr))

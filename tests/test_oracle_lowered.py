@@ -181,3 +181,65 @@ def test_gemv_rows_beta_zero_does_not_read_y():
     got = LW.evaluate_gemv_rows([[1.0] * 8], [2.0] * 8, 0.5, 0.0, [float("nan")], s, add=F.add, mul=F.mul, fma=F.fma,
                                 zero=0.0)
     assert got == [8.0]
+
+
+# ---------------------------------------------------------------- lane forms
+
+LANE_FORMS = {1: "reorder-stride lanes, folded in lane order", 2: "contiguous runs, tree",
+              3: "contiguous runs, folded in lane order"}
+
+
+@pytest.mark.parametrize("form", sorted(LANE_FORMS))
+def test_lane_forms_are_valid_derivations(form):
+    r = random.Random(form)
+    blocks = (64, 256, 1024) if form == 2 else (1, 2, 32, 64, 256)
+    for block in blocks:
+        for _ in range(6):
+            eb, vb = r.choice([(4, 4), (4, 16), (2, 2), (2, 8)])
+            unroll = r.choice([1, 2, 4, 8])
+            split = r.choice([256, 4096, 1 << 15])
+            n = r.choice([0, 1, 7, 1000, 4099, 20_001])
+            mis = r.randrange(vb // eb)
+            x = ints(n, block + n + form)
+            s = LW.launch_shape(n, eb, vb, block, unroll, split, misalign_elems=mis, lane_form=form)
+            assert s.runs == bool(form & 2) and s.seq == bool(form & 1)
+            assert s.final_lanes == min(64, block)
+            assert LW.evaluate(x, s, **EXACT) == sum(abs(v) for v in x), (form, block, vb, unroll, split, n, mis)
+            y = ints(n, n + 3)
+            exact = dict(add=lambda a, b: a + b, fma=lambda a, b, c: a * b + c, zero=0)
+            assert LW.evaluate_dot(x, y, s, **exact) == sum(a * b for a, b in zip(x, y))
+
+
+def _order(n, block, form, unroll=1, chunk_elems=None):
+    """The order in which one work-group's expression folds x[0..n) (scalar
+    vectors): a tracing arithmetic whose sums are tuple concatenations."""
+    s = LW.launch_shape(n, 4, 4, block, unroll, chunk_elems or n, lane_form=form)
+    assert s.grid == 1
+    trace = dict(add=lambda a, b: a + b, absval=lambda v: () if v == () else (v,), zero=())
+    return LW.evaluate(list(range(1, n + 1)), s, **trace)
+
+
+def test_lane_form_partitions():
+    # contiguous runs folded in lane order read the chunk front to back
+    assert _order(64, 4, 3) == tuple(range(1, 65))
+    # reorder-stride lanes folded in lane order: lane t takes t, t + B, ...
+    B = 4
+    assert _order(64, B, 1) == tuple(v + 1 for t in range(B) for v in range(t, 64, B))
+    # contiguous runs of 16 under the tree: 64 lanes -> runs of one vector
+    # for 64 elements; with 256 elements each lane folds its own run of 4
+    got = _order(256, 64, 2)
+    runs = [tuple(range(4 * t + 1, 4 * t + 5)) for t in range(64)]
+    assert sorted(got) == list(range(1, 257))
+    pos = {v: i for i, v in enumerate(got)}
+    for run in runs:        # each run stays together and in order inside the tree
+        idx = [pos[v] for v in run]
+        assert idx == list(range(idx[0], idx[0] + 4))
+
+
+def test_single_lane_form_is_fig9c_on_integers():
+    # one lane per work-group over contiguous runs (Fig. 9c): 32768 floats
+    # per work-group as 8192 float4, one lane
+    s = LW.launch_shape(32768 * 3, 4, 16, 1, 1, 32768, lane_form=3)
+    assert s.grid == 3 and s.chunk == 8192 and s.final_lanes == 1
+    x = ints(32768 * 3, 9)
+    assert LW.evaluate(x, s, **EXACT) == P.asum_lowlevel_cpu(32768, 8192, 4)(x)[0] == sum(abs(v) for v in x)

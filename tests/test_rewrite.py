@@ -100,11 +100,16 @@ def test_fig9b_shape_is_derived():
         "map-local(reduce-seq(vect-4(absAndPlus), vect-4(0))) o split-2 o reorder-stride-256) o "
         "split-512 o asVector-4")
     assert R.kernel_knobs(d) == {"block": 256, "vec_bytes": 16, "split": 2048, "interleave": R.INTERLEAVE_CHUNK}
-    # Fig. 9c: one lane per work-group, no reorder -- derived, but not this library's kernel
+    # Fig. 9c: one lane per work-group, no reorder -- the kernel of the
+    # contiguous-runs form folded in lane order, with a block of one lane
     d = R.derive_one("asum", R.Choice(32768, 4, 8192, False, False))
     assert str(d.expr) == ("reduce-seq(plus, 0) o asScalar o join o map-workgroup(reduce-seq(vect-4(absAndPlus), "
                            "vect-4(0))) o split-8192 o asVector-4")
-    assert R.kernel_knobs(d) is None
+    assert R.kernel_knobs(d) == {"block": 1, "vec_bytes": 16, "split": 32768, "interleave": R.INTERLEAVE_CHUNK,
+                                 "lane_form": R.LANES_SEQ | R.LANES_RUNS}
+    # past 1024 lanes no kernel exists
+    assert R.kernel_knobs(R.derive_one("asum", R.Choice(1 << 13, 1, 4, True, True))) is None
+    assert R.kernel_knobs(R.derive_one("asum", R.Choice(1 << 14, 1, 8, True, True))) is None
 
 
 def test_fig8_prefix_is_the_papers_derivation():
@@ -156,13 +161,26 @@ def test_rules_check_their_preconditions():
         R.derive_one("asum", R.Choice(4096, 1, 3, True, True))   # 4096/3 lanes: not a power of two
 
 
-def test_unimplementable_forms_get_no_kernel():
-    n = 1 << 20
-    for d in R.derive_reduction("asum", n):
-        c = R._choice_of(d)
-        k = R.kernel_knobs(d)
-        ok = c.reorder and c.tree and 64 <= c.lanes <= 1024
-        assert (k is not None) == ok
+def test_every_derived_reduction_gets_its_lane_form():
+    # every derivation of the search has a launch: the default kernel for
+    # reorder-stride lanes under the tree, the lane-form kernel for the
+    # other three forms (down to one lane per work-group), each knob set
+    # naming the partition the derivation chose
+    for op in ("asum", "dot"):
+        for n in (1 << 20, 1 << 24):
+            ds = list(R.derive_reduction(op, n))
+            assert len(ds) > 1000
+            forms = set()
+            for d in ds:
+                c = R._choice_of(d)
+                k = R.kernel_knobs(d)
+                assert k is not None and 1 <= c.lanes <= 1024, str(d.expr)
+                form = k.get("lane_form", 0)
+                forms.add(form)
+                assert form == (0 if c.tree else R.LANES_SEQ) | (0 if c.reorder else R.LANES_RUNS)
+                assert k["block"] == c.lanes and k["split"] == c.chunk
+                assert k["block"] >= 64 or form == R.LANES_SEQ | R.LANES_RUNS
+            assert forms == {0, 1, 2, 3}
 
 
 def test_scal_derivations_are_exact_and_match_the_launch_rules():

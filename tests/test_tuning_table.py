@@ -135,9 +135,9 @@ def test_force_config_overrides_tuned_and_defaults():
     assert src == 2
     assert (k["block"], k["unroll"], k["split"], k["interleave"], k["wg_per_cu"], k["vec_bytes"]) == \
         (512, 2, 65536, L.LIFT_INTERLEAVE_STRIDE, 4, 8)
-    src, k = _child(QUERY, "wg=128,rpw=2,rowsplit=1,lanes=8,interleave=2")
-    assert src == 2 and (k["block"], k["rows_per_wave"], k["row_split"], k["lanes_per_item"], k["interleave"]) == \
-        (128, 2, 1, 8, L.LIFT_INTERLEAVE_CHUNK)
+    src, k = _child(QUERY, "wg=128,rpw=2,rowsplit=1,lanes=8,interleave=2,laneform=3")
+    assert src == 2 and (k["block"], k["rows_per_wave"], k["row_split"], k["lanes_per_item"], k["interleave"],
+                         k["lane_form"]) == (128, 2, 1, 8, L.LIFT_INTERLEAVE_CHUNK, L.LIFT_LANES_RUNS_SEQ)
 
 
 @pytest.mark.parametrize("bad", ["block", "block=", "block=abc", "blocks=256", "block=-64", "block=256;unroll=2",
