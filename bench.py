@@ -101,8 +101,9 @@ def main():
     ap.add_argument("--event-every", type=int, default=20,
                     help="time the dominant kernel in every k-th step of the timed region")
     ap.add_argument("--stamps", default=None, metavar="OPS",
-                    help="diagnostic only: per-work-group clock stamps of the step's asum / dot launches "
-                         "(e.g. asum,dot); prints a JSON summary and exits")
+                    help="diagnostic only: per-work-group clock stamps of the step's asum / dot launches, "
+                         "per-tile stamps of the batched workload's two launches (e.g. asum,dot,batch); "
+                         "prints a JSON summary and exits")
     ap.add_argument("--stamp-n", type=int, default=24, help="log2 n for --stamps")
     args = ap.parse_args()
 
@@ -126,7 +127,14 @@ def main():
     log("device", props.name, "CUs", props.multi_processor_count, "lib", L.lift_version())
 
     if args.stamps:
-        print(json.dumps(stamp_report(L, W, dev, stream, args.stamps.split(","), 1 << args.stamp_n)), flush=True)
+        ops = args.stamps.split(",")
+        out = {}
+        if "batch" in ops:
+            out["batch"] = batch_stamp_report(L, W, dev)
+            ops = [o for o in ops if o != "batch"]
+        if ops:
+            out.update(stamp_report(L, W, dev, stream, ops, 1 << args.stamp_n))
+        print(json.dumps(out), flush=True)
         return
 
     # ------------------------------------------------------------ main step
@@ -363,6 +371,109 @@ def stamp_report(L, W, dev, stream, ops, n, launches=40):
         summary["knobs"] = L.lift_default_knobs(op, L.LIFT_F32, 0, n)[1]
         out[op] = summary
         log("stamps", op, summary)
+    return out
+
+
+def batch_stamp_report(L, W, dev, runs=4):
+    """Where the batched workload's time goes, from per-tile wall-clock
+    stamps (lift_stamp_next_launch on lift_batch_run) of `runs` runs per
+    storage.  Per launch (reduction tiles, gemv tiles) of the last run: its
+    span from the first tile's start, the work-groups, busy time per
+    work-group (median), the gaps between a work-group's tiles (mean sum per
+    work-group), the spread of the work-groups' last tile ends, and the
+    algorithmic GB/s over the span; for the gemv launch, the rate per
+    work-group by row class (rows starting on a vector boundary, rows with
+    heads against shifted copies of x, element loads) and row length."""
+    import torch
+    import numpy as np
+
+    spec = W.batch_shapes()
+    nred = len(spec.red_kind)
+    out = {}
+    for storage, eb in (("bf16", 2), ("f32", 4)):
+        reds, gemvs = W.batch_values(spec, storage)
+        probs = []
+        for kind, x, y in reds:
+            probs.append(("dot", x.to(dev), y.to(dev)) if kind == "dot" else ("asum", x.to(dev)))
+        for A, x, y in gemvs:
+            probs.append(("gemv", W.GEMV_ALPHA, A.to(dev), x.to(dev), W.GEMV_BETA, y.to(dev)))
+        del reds, gemvs
+        b = L.Batch(probs)
+        _, kn = L.lift_default_knobs("batch", {"f32": L.LIFT_F32, "bf16": L.LIFT_BF16}[storage], L.LIFT_ACC_F32, 0)
+        vb = kn["vec_bytes"] or 16          # the library default when no tuned entry applies
+        buf = torch.zeros((b.tiles, 4), dtype=torch.int64, device=dev)
+        ev = L.HipEvents(2)
+        for _ in range(2):
+            b.run()
+        torch.cuda.synchronize()
+        run_us = []
+        for _ in range(runs):
+            buf.zero_()
+            torch.cuda.synchronize()
+            st, khz = L.lift_stamp_next_launch(buf.data_ptr(), b.tiles)
+            assert st == 0 and khz > 0
+            assert L.lift_time_next_launch(ev.events[0], ev.events[1]) == 0
+            b.run()
+            torch.cuda.synchronize()
+            run_us.append(ev.elapsed_ms(0, 1) * 1e3)
+        ev.close()
+        t = buf.cpu().numpy().astype(np.int64)
+        us = 1e3 / khz
+        prob = t[:, 2] >> 32
+        length = t[:, 2] & 0xFFFFFFFF
+        rep = {"run_us": [round(v, 1) for v in run_us], "knobs": kn}
+        ntiles = np.bincount(prob[prob < nred], minlength=nred)
+        for name, mask in (("reductions", prob < nred), ("gemv", prob >= nred)):
+            a, p, ln = t[mask], prob[mask], length[mask]
+            t0 = a[:, 0].min()
+            s, e = (a[:, 0] - t0) * us, (a[:, 1] - t0) * us
+            wg = a[:, 3] & 0xFFFFFFFF
+            if name == "reductions":
+                n = np.array([spec.red_len[i] for i in p])
+                opnd = np.array([2 if spec.red_kind[i] == "dot" else 1 for i in p])
+                tb = n / ntiles[p] * eb * opnd                     # a problem's bytes over its tiles
+            else:
+                mn = np.array([spec.gemv_mn[i - nred] for i in p])
+                n = mn[:, 1]
+                tb = ln * n * eb
+            groups = np.unique(wg)
+            busy, gaps, last = [], [], []
+            for g in groups:
+                m = wg == g
+                o = np.argsort(s[m])
+                gs, ge = s[m][o], e[m][o]
+                busy.append(float((ge - gs).sum()))
+                gaps.append(float((gs[1:] - ge[:-1]).sum()))
+                last.append(float(ge.max()))
+            span = float(e.max())
+            r = {"tiles": int(mask.sum()), "work_groups": int(len(groups)), "span_us": round(span, 1),
+                 "GB_s_over_span": round(float(tb.sum()) / span / 1e3, 1),
+                 "busy_us_per_wg_median": round(float(np.median(busy)), 1),
+                 "gaps_us_per_wg_mean": round(float(np.mean(gaps)), 1),
+                 "last_end_us_min_median_max": [round(min(last), 1), round(float(np.median(last)), 1),
+                                                round(max(last), 1)],
+                 "tile_us_p10_p50_p90": [round(float(np.percentile(e - s, q)), 1) for q in (10, 50, 90)]}
+            if name == "gemv":
+                aptr = np.array([probs[i][2].data_ptr() for i in p], dtype=np.int64)
+                E = vb // eb
+                aligned = ((n * eb) % vb == 0) & (aptr % vb == 0)
+                heads = ~aligned & (E > 1) & (vb <= 8) & (n >= 64 * E) & (E * ((n + 3) // 4 * 4) <= 16320)
+                classes = {}
+                dur = e - s
+                for cname, cm in (("aligned", aligned), ("heads", heads), ("elements", ~aligned & ~heads)):
+                    for lo, hi in ((0, 1024), (1024, 2048), (2048, 4097)):
+                        mm = cm & (n >= lo) & (n < hi)
+                        if mm.sum():
+                            classes[f"{cname} n in [{lo},{hi})"] = {
+                                "tiles": int(mm.sum()), "GB": round(float(tb[mm].sum()) / 1e9, 3),
+                                "GB_s_per_wg": round(float(tb[mm].sum()) / float(dur[mm].sum()) / 1e3, 2)}
+                r["rows"] = classes
+            rep[name] = r
+        out[storage] = rep
+        log("batch stamps", storage, rep)
+        b.close()
+        del probs
+        torch.cuda.empty_cache()
     return out
 
 

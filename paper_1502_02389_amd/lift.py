@@ -235,8 +235,8 @@ def lift_default_knobs(op, storage, acc, elements, arch=None, cus=0, row_length=
 
 
 def lift_stamp_next_launch(stamps, capacity):
-    """Arm the stamped instance for the next asum / dot launch; returns
-    (status, clock rate in kHz)."""
+    """Arm the stamped instances for the next asum / dot launch or batch run
+    (see lift_stamp_next_launch in lift.h); returns (status, clock rate in kHz)."""
     khz = ctypes.c_int32(0)
     st = _lib().lift_stamp_next_launch(stamps, capacity, ctypes.byref(khz) if stamps else None)
     return st, khz.value
