@@ -421,17 +421,27 @@ __global__ void __launch_bounds__(512) batch_kernel(BatchArgs a)
             const BT wg = block_sum<BT>(v, lds_block);
 
             if (t == 0) {
-                store_coherent(a.slots + (p.slot_base + tl.index) * WS_SLOT, to_slot<ACC>(wg));
-                // the next tile is drawn here, its round trip overlapping the
-                // partial's store (the work-group is all but done with this one)
-                const unsigned ticket =
-                    __hip_atomic_fetch_add(&a.counters[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                unsigned prev = __hip_atomic_fetch_add(&a.pcount[tl.problem], 1u, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                s_last = prev == (unsigned)(p.ntiles - 1);
+                unsigned ticket;
+                if (p.ntiles == 1) {
+                    // a problem of one tile: the combine of a single partial
+                    // returns it unchanged (it adds zeros to a sum that is
+                    // never -0), so the partial is the result, written
+                    // without the slot, the count and the combine
+                    write_result(p.out, a.result_f64, to_slot<ACC>(wg));
+                    ticket = __hip_atomic_fetch_add(&a.counters[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_last = 0;
+                } else {
+                    store_coherent(a.slots + (p.slot_base + tl.index) * WS_SLOT, to_slot<ACC>(wg));
+                    // the next tile is drawn here, its round trip overlapping the
+                    // partial's store (the work-group is all but done with this one)
+                    ticket = __hip_atomic_fetch_add(&a.counters[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    __builtin_amdgcn_s_waitcnt(0);  // the partial's store has completed
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    unsigned prev = __hip_atomic_fetch_add(&a.pcount[tl.problem], 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                    s_last = prev == (unsigned)(p.ntiles - 1);
+                }
                 s_tile = (int)gridDim.x + (int)ticket;
             }
             __syncthreads();
