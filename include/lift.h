@@ -366,7 +366,10 @@ typedef struct lift_problem {
 typedef struct lift_batch lift_batch;
 
 /* Plan a batch on the current device: checks every problem as the per-call
- * entry points do, builds the tile table (tiles sorted largest first), and
+ * entry points do, builds the tile table (tiles sorted largest first; the
+ * gemv launch's last round of tiles, one per work-group, cut in quarters of
+ * whole row groups; each launch's grid at most knobs.wg_per_cu work-groups
+ * per compute unit and no more than the kernel keeps resident), and
  * allocates and fills one device buffer for descriptors, tiles, partial
  * slots and counters (this call allocates and synchronises; lift_batch_run
  * does neither).  storage: F32, BF16 or F16 for every x, y and A; rt: F32 or
@@ -383,7 +386,8 @@ lift_status lift_batch_create(const lift_problem *probs, int32_t count, lift_dty
  * the call can be captured into a HIP graph and replayed.  Runs of one batch
  * must not overlap (they share the counters).  An armed timing hook
  * (lift_time_next_launch) spans the whole run: start with the first launch,
- * stop with the last. */
+ * stop with the last; an armed stamp hook (lift_stamp_next_launch) makes
+ * both launches stamped. */
 lift_status lift_batch_run(lift_batch *batch, hipStream_t stream);
 
 /* Capture lift_batch_run on `stream` (which must not be the null stream)

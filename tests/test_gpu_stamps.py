@@ -102,3 +102,35 @@ def test_batch_stamps(gpu_device, storage):
     for j, (m, n) in enumerate(spec.gemv_mn):
         assert int(length[prob == n_red + j].sum()) == m, ("rows of gemv", j)
     b.close()
+
+
+def test_batch_stamps_gemv_only_and_small_capacity(gpu_device):
+    """A batch of gemv problems only: its records start at word 0; a
+    capacity below the tile count is rejected and clears the hook, and the
+    next run is plain."""
+    banner("batch stamps gemv only")
+    spec = small_spec(seed=74, n_red=0, n_gemv=6)
+    cpu, problems = build(spec, storage="f32", seed=75)
+    b = L.Batch(problems)
+    cap = b.tiles
+    buf = torch.zeros((cap, 4), dtype=torch.int64, device=DEV)
+    torch.cuda.synchronize()
+    st, _ = L.lift_stamp_next_launch(buf.data_ptr(), cap - 1)
+    assert st == 0
+    with pytest.raises(L.LiftError) as e:
+        b.run()
+    assert e.value.status == L.LIFT_EINVAL
+    b.run()                     # the hook is cleared: a plain run
+    torch.cuda.synchronize()
+    assert not buf.cpu().numpy().any()
+    st, _ = L.lift_stamp_next_launch(buf.data_ptr(), cap)
+    assert st == 0
+    b.run()
+    torch.cuda.synchronize()
+    t = buf.cpu().numpy()
+    assert np.all(t[:, 0] != 0) and np.all(t[:, 1] >= t[:, 0])
+    length = t[:, 2] & 0xFFFFFFFF
+    prob = t[:, 2] >> 32
+    for j, (m, n) in enumerate(spec.gemv_mn):
+        assert int(length[prob == j].sum()) == m
+    b.close()
