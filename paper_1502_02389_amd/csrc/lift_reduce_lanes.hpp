@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(1024) reduce_lanes_kernel(ReduceArgs a)
     constexpr int E = Elems<T, VB>::value;
     using V = typename Vec<VB>::type;
     __shared__ float lds_block[16];
-    __shared__ float lds_lane[SEQ ? 1024 : 1];
+    __shared__ float lds_lane[SEQ ? 1024 : 64];
     __shared__ int s_last;
 
     const int t = threadIdx.x;
@@ -132,12 +132,12 @@ __global__ void __launch_bounds__(1024) reduce_lanes_kernel(ReduceArgs a)
     } else {
         wg = block_sum<float>(acc.value(), lds_block);
     }
-    if (B >= 64) {
+    if (!SEQ || B >= 64) {   // tree forms run 64 or more lanes (the host checks)
         combine_partials<ACC, false>(a, wg);
         return;
     }
 
-    // B < 64: the combine over B lanes
+    // B < 64 (sequential forms): the combine over B lanes
     if (gridDim.x == 1) {
         if (t == 0)
             write_result(a.result, a.result_f64, wg);
