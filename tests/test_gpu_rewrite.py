@@ -85,3 +85,24 @@ def test_every_lane_form_derivation_runs_integer_exact(gpu_device, storage):
             k = L.knobs(**kn)
             got = L.asum(xd, knobs=k).item() if op == "asum" else L.dot(xd, yd, knobs=k).item()
             assert got == (ra if op == "asum" else rd), (kn, str(d.expr))
+
+
+@pytest.mark.parametrize("form", [1, 2, 3])
+def test_lane_forms_small_and_ragged_sizes_exact(gpu_device, form):
+    """The other lane forms at empty, tiny and ragged sizes, misaligned
+    starts and the smallest blocks: exact sums on integer inputs."""
+    g = W.gen(84 + form)
+    blocks = (64, 256) if form == 2 else (1, 4, 64)
+    for n in (0, 1, 5, 63, 64, 65, 1000, 4099):
+        x = W.integers(n + 3, -8, 8, g)
+        y = W.integers(n + 3, -4, 4, g)
+        for off in (0, 1, 3):
+            xs, ys = x[off:off + n], y[off:off + n]
+            xd, yd = x.to(DEV)[off:off + n], y.to(DEV)[off:off + n]
+            ra, rd = o_asum(xs), o_dot(xs, ys)[0]
+            for block in blocks:
+                for vb, u in ((16, 2), (4, 1)):
+                    k = L.knobs(block=block, vec_bytes=vb, unroll=u, split=block * u * 8, lane_form=form)
+                    banner("lane form small", form, n, off, block, vb, u)
+                    assert L.asum(xd, knobs=k).item() == ra, (form, n, off, block, vb, u)
+                    assert L.dot(xd, yd, knobs=k).item() == rd, (form, n, off, block, vb, u)
