@@ -2,19 +2,22 @@
 //
 // The paper's split and map-workgroup over a list of problems.  The host cuts
 // every problem into tiles (reductions: runs of vectors; gemv: runs of rows)
-// and sorts each kind's tiles largest first.  A run is two persistent
-// launches on one stream, one per kind, so that each kernel is compiled for
-// its own work (its register peak sets how many work-groups a CU holds, and
-// the reductions' need not limit the gemv's).  In each, work-groups take the
+// and sorts each kind's tiles largest first (the gemv launch's last round
+// of tiles cut in quarters).  A run is two persistent launches on one
+// stream, one per kind, so that each kernel is compiled for its own work
+// (its register peak sets how many work-groups a CU holds, and the
+// reductions' need not limit the gemv's); each grid holds no more
+// work-groups than the CUs keep resident.  In each, work-groups take the
 // next tile from an agent-scope counter until the table is exhausted:
 //   reduction tile -> the per-call streaming body (lane reduce-seq, DPP wave
 //                     butterfly, LDS across waves) -> partial slot of the tile;
 //                     the work-group that finishes a problem's last tile folds
 //                     that problem's partials in tile order and writes its
-//                     result;
-//   gemv tile      -> each wavefront takes pairs of the tile's rows
-//                     (gemv_row_group); where x fits, the work-group first
-//                     copies it into LDS and the rows read it there.
+//                     result (a one-tile problem writes its partial directly);
+//   gemv tile      -> each wavefront takes pairs of the tile's rows; where x
+//                     fits, the work-group first copies it into LDS (for rows
+//                     with heads, E copies shifted by one element each) and
+//                     the rows read it there.
 // Tile-to-work-group assignment is dynamic, but every tile's arithmetic and
 // every combine order are fixed by the plan, so results are deterministic.
 // The last work-group to leave a launch resets that launch's counters, so a
