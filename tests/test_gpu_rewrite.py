@@ -106,3 +106,16 @@ def test_lane_forms_small_and_ragged_sizes_exact(gpu_device, form):
                     banner("lane form small", form, n, off, block, vb, u)
                     assert L.asum(xd, knobs=k).item() == ra, (form, n, off, block, vb, u)
                     assert L.dot(xd, yd, knobs=k).item() == rd, (form, n, off, block, vb, u)
+
+
+def test_lane_forms_binary64_result(gpu_device):
+    """A lane form with a binary64 result: the binary32 value widened, equal
+    to the binary32-result call's value."""
+    g = W.gen(88)
+    x = W.uniform((1 << 18) + 5, g).to(DEV)
+    y = W.uniform((1 << 18) + 5, g).to(DEV)
+    for form in (1, 2, 3):
+        k = L.knobs(block=64 if form == 2 else 16, vec_bytes=16, unroll=2, split=1 << 12, lane_form=form)
+        a32, a64 = L.asum(x, knobs=k).item(), L.asum(x, knobs=k, result_dtype=torch.float64).item()
+        d32, d64 = L.dot(x, y, knobs=k).item(), L.dot(x, y, knobs=k, result_dtype=torch.float64).item()
+        assert a64 == a32 and d64 == d32, form

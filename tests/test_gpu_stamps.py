@@ -134,3 +134,30 @@ def test_batch_stamps_gemv_only_and_small_capacity(gpu_device):
     for j, (m, n) in enumerate(spec.gemv_mn):
         assert int(length[prob == j].sum()) == m
     b.close()
+
+
+def test_stamp_hook_rejects_unstamped_kinds(gpu_device):
+    """The stamped instances exist for binary32 accumulation with F32 or BF16
+    storage: a batch in F16 storage, or with compensated accumulation, fails
+    the armed run with LIFT_EUNSUPPORTED and clears the hook; a lane-form
+    asum does the same."""
+    banner("stamps unsupported kinds")
+    buf = torch.zeros((4096, 8), dtype=torch.int64, device=DEV)
+    for storage, acc in (("f16", "f32"), ("bf16", "comp")):
+        cpu, problems = build(small_spec(seed=76, n_red=8, n_gemv=2), storage=storage, seed=77)
+        b = L.Batch(problems, acc=acc)
+        st, _ = L.lift_stamp_next_launch(buf.data_ptr(), 4096)
+        assert st == 0
+        with pytest.raises(L.LiftError) as e:
+            b.run()
+        assert e.value.status == L.LIFT_EUNSUPPORTED
+        b.run()                      # hook cleared: a plain run
+        torch.cuda.synchronize()
+        b.close()
+    x = W.uniform(1 << 16, W.gen(78)).to(DEV)
+    st, _ = L.lift_stamp_next_launch(buf.data_ptr(), 4096)
+    assert st == 0
+    with pytest.raises(L.LiftError) as e:
+        L.asum(x, knobs=L.knobs(lane_form=L.LIFT_LANES_SEQ))
+    assert e.value.status == L.LIFT_EUNSUPPORTED
+    assert L.asum(x, knobs=L.knobs(lane_form=L.LIFT_LANES_SEQ)).item() > 0
